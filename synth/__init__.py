@@ -1,0 +1,198 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the bench.
+
+This module only draws random numbers and shapes them into the channel model
+of a decode workload: random message bits, and per-codeword error positions
+turned into flip masks.  It contains none of the decoder's arithmetic (no
+parity, syndrome, correction or extraction).  Turning messages into codewords
+is left to an encoder: the CPU oracle in the tests, the library's own encoder
+where the bench prepares device-resident inputs.
+
+Generator: SplitMix64 (G. L. Steele, D. Lea, C. H. Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014), used counter-style: draw ``c``
+of a stream seeded with ``s`` is ``mix64(s + (c + 1) * GAMMA)``, which is the
+c-th output of SplitMix64 started from state ``s``.  Any slice of a stream can
+be produced independently, so results do not depend on chunking or threads.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+_MASK64 = (1 << 64) - 1
+BASE_SEED = 0x14126862
+_CHUNK = 1 << 22
+
+
+def mix64(z: np.ndarray) -> np.ndarray:
+    """SplitMix64 output function on a uint64 array (wrapping arithmetic)."""
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def mix64_int(z: int) -> int:
+    """Scalar SplitMix64 output function on a Python int (mod 2^64)."""
+    z &= _MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+    return z ^ (z >> 31)
+
+
+def subseed(base: int, *tags: int | str) -> int:
+    """Derive an independent stream seed from a base seed and tags."""
+    s = base & _MASK64
+    for t in tags:
+        if isinstance(t, str):
+            v = 0
+            for ch in t.encode():
+                v = (v * 131 + ch) & _MASK64
+            t = v
+        s = mix64_int(s ^ mix64_int((int(t) + 0x632BE59BD9B4E019) & _MASK64))
+    return s
+
+
+def draws(seed: int, start: int, count: int) -> np.ndarray:
+    """Draws ``start .. start+count-1`` of the stream seeded with ``seed``."""
+    ctr = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        state = np.uint64(seed & _MASK64) + ctr * GAMMA
+    return mix64(state)
+
+
+def code_sizes(r: int) -> tuple[int, int, int]:
+    """(n, k, storage words per codeword) of the (2^r-1, 2^r-1-r) code."""
+    if not 3 <= r <= 7:
+        raise ValueError("r must be in [3, 7]")
+    n = (1 << r) - 1
+    return n, n - r, (2 if r == 7 else 1)
+
+
+def message_stream(seed: int, n_cw: int, r: int) -> np.ndarray:
+    """Uniform random message bits for n_cw codewords as a dense stream.
+
+    Returns uint64 words, ceil(n_cw*k/64) of them; the bits after n_cw*k are 0.
+    Every message bit is an independent fair coin, i.e. data i.i.d.
+    Bernoulli(0.5).
+    """
+    _, k, _ = code_sizes(r)
+    bits = n_cw * k
+    nwords = (bits + 63) // 64
+    out = np.empty(nwords, dtype=np.uint64)
+    for a in range(0, nwords, _CHUNK):
+        b = min(nwords, a + _CHUNK)
+        out[a:b] = draws(seed, a, b - a)
+    tail = bits % 64
+    if nwords and tail:
+        out[-1] &= np.uint64((1 << tail) - 1)
+    return out
+
+
+def _threshold(prob: float) -> int:
+    """Integer threshold t such that a 53-bit uniform u is below t with
+    probability ``prob`` (exact for prob = 0 and prob = 1)."""
+    if not 0.0 <= prob <= 1.0:
+        raise ValueError("probability out of range")
+    return int(math.floor(prob * (1 << 53)))
+
+
+def _first_position(u: np.ndarray, n: int) -> np.ndarray:
+    return np.uint64(1) + (((u >> np.uint64(32)) * np.uint64(n)) >> np.uint64(32))
+
+
+def _second_position(u: np.ndarray, first: np.ndarray, n: int) -> np.ndarray:
+    step = np.uint64(1) + (((u & np.uint64(0xFFFFFFFF)) * np.uint64(n - 1)) >> np.uint64(32))
+    return np.uint64(1) + ((first - np.uint64(1) + step) % np.uint64(n))
+
+
+def error_positions(seed: int, n_cw: int, r: int, p_single: float = 0.0,
+                    p_double: float = 0.0) -> tuple[np.ndarray, np.ndarray]:
+    """Per-codeword channel errors.
+
+    Each codeword independently gets one flipped bit with probability
+    ``p_single``, two distinct flipped bits with probability ``p_double`` and
+    none otherwise.  Positions are uniform over all n positions (parity
+    positions included); the two positions of a double error are a uniform
+    unordered pair.  Returns (pos1, pos2) uint8 arrays, 0 meaning "no flip".
+    """
+    n, _, _ = code_sizes(r)
+    t1 = _threshold(p_single)
+    t2 = _threshold(min(1.0, p_single + p_double))
+    s_kind = subseed(seed, "kind")
+    s_pos = subseed(seed, "pos")
+    pos1 = np.zeros(n_cw, dtype=np.uint8)
+    pos2 = np.zeros(n_cw, dtype=np.uint8)
+    for a in range(0, n_cw, _CHUNK):
+        b = min(n_cw, a + _CHUNK)
+        u = draws(s_kind, a, b - a) >> np.uint64(11)
+        one = u < np.uint64(t1)
+        two = (u >= np.uint64(t1)) & (u < np.uint64(t2))
+        v = draws(s_pos, a, b - a)
+        first = _first_position(v, n)
+        second = _second_position(v, first, n)
+        pos1[a:b] = np.where(one | two, first, 0).astype(np.uint8)
+        pos2[a:b] = np.where(two, second, 0).astype(np.uint8)
+    return pos1, pos2
+
+
+def flip_masks(pos1: np.ndarray, pos2: np.ndarray, r: int) -> np.ndarray:
+    """Storage-layout flip masks (bit p-1 for position p) for the positions."""
+    _, _, wpc = code_sizes(r)
+    n_cw = pos1.size
+    masks = np.zeros((n_cw, wpc), dtype=np.uint64)
+    for pos in (pos1, pos2):
+        pos = pos.astype(np.int64)
+        has = pos > 0
+        bit = np.where(has, pos - 1, 0)
+        word = bit // 64
+        val = np.where(has, np.left_shift(np.uint64(1), (bit % 64).astype(np.uint64)), np.uint64(0))
+        for w in range(wpc):
+            masks[:, w] ^= np.where(word == w, val, np.uint64(0))
+    return masks.reshape(-1)
+
+
+def padding_garbage(seed: int, n_cw: int, r: int) -> np.ndarray:
+    """Random bits in the storage padding (bits at or above n) of each
+    codeword, zero elsewhere.  A decoder must ignore them."""
+    n, _, wpc = code_sizes(r)
+    g = np.empty(n_cw * wpc, dtype=np.uint64)
+    for a in range(0, g.size, _CHUNK):
+        b = min(g.size, a + _CHUNK)
+        g[a:b] = draws(subseed(seed, "garbage"), a, b - a)
+    g = g.reshape(n_cw, wpc)
+    valid = [(1 << min(64, max(0, n - 64 * w))) - 1 for w in range(wpc)]
+    for w in range(wpc):
+        g[:, w] &= np.uint64(~valid[w] & _MASK64)
+    return g.reshape(-1)
+
+
+# --- workload recipes ------------------------------------------------------
+
+PLAIN_ERROR_RATES = (0.0, 0.01, 0.1, 0.5, 1.0)
+
+
+def workload_seed(tag: str, r: int, extra: int | str = 0) -> int:
+    return subseed(BASE_SEED, tag, r, extra)
+
+
+def batch_packets(seed: int, n_packets: int, min_cw: int = 64, max_log2_span: int = 14,
+                  r_values=(3, 4, 5, 6, 7), max_p: float = 0.5):
+    """Packet list of a batched workload: sizes log-uniform in
+    [min_cw, min_cw * 2^max_log2_span], r uniform over ``r_values``, per-packet
+    single-error rate uniform in [0, max_p].  Returns (n_cw, r, p) arrays."""
+    u = draws(subseed(seed, "sizes"), 0, n_packets)
+    ur = draws(subseed(seed, "rs"), 0, n_packets)
+    up = draws(subseed(seed, "ps"), 0, n_packets)
+    f_u = (u >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+    f_r = (ur >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+    f_p = (up >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+    n_cw = np.floor(min_cw * np.exp2(max_log2_span * f_u)).astype(np.int64)
+    rv = np.asarray(r_values, dtype=np.int64)
+    r = rv[np.minimum((f_r * len(rv)).astype(np.int64), len(rv) - 1)]
+    p = max_p * f_p
+    return n_cw, r, p
