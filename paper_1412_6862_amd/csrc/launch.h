@@ -1,0 +1,34 @@
+// Internal launch interface between the C ABI and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hm {
+
+// Kernel flag bits, decided on the host from pointer alignment.
+constexpr uint32_t kFlagIn16 = 1u;    // codeword input is 16-byte aligned
+constexpr uint32_t kFlagEpVec = 2u;   // errpos output is aligned to U bytes
+
+struct DecodeLaunch {
+    int r;
+    int u;                  // codewords per lane
+    const uint64_t* cw;
+    uint64_t n_cw;
+    uint64_t* data;
+    uint64_t data_words;
+    uint8_t* errpos;
+    uint64_t max_blocks;    // 0 = one wave per tile
+};
+
+// Smallest lane width that gives every lane chunk at least one dword.
+constexpr bool valid_u(int r, int u)
+{
+    const int k = (1 << r) - 1 - r;
+    return (u == 2 || u == 4 || u == 8 || u == 16) && u * k >= 32;
+}
+
+hipError_t launch_decode(const DecodeLaunch& L, hipStream_t stream);
+hipError_t launch_encode(int r, const void* stream_in, uint64_t n_cw, uint64_t* out, hipStream_t stream);
+
+}  // namespace hm

@@ -16,6 +16,8 @@ be produced independently, so results do not depend on chunking or threads.
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -25,6 +27,22 @@ _M2 = np.uint64(0x94D049BB133111EB)
 _MASK64 = (1 << 64) - 1
 BASE_SEED = 0x14126862
 _CHUNK = 1 << 22
+
+
+def _workers() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _chunked(total: int, fn) -> None:
+    """Run fn(a, b) over [0, total) in chunks, on a thread pool (numpy
+    releases the GIL inside its loops).  Results must not depend on order."""
+    spans = [(a, min(total, a + _CHUNK)) for a in range(0, total, _CHUNK)]
+    if len(spans) <= 1:
+        for a, b in spans:
+            fn(a, b)
+        return
+    with ThreadPoolExecutor(_workers()) as ex:
+        list(ex.map(lambda ab: fn(*ab), spans))
 
 
 def mix64(z: np.ndarray) -> np.ndarray:
@@ -84,9 +102,11 @@ def message_stream(seed: int, n_cw: int, r: int) -> np.ndarray:
     bits = n_cw * k
     nwords = (bits + 63) // 64
     out = np.empty(nwords, dtype=np.uint64)
-    for a in range(0, nwords, _CHUNK):
-        b = min(nwords, a + _CHUNK)
+
+    def fill(a, b):
         out[a:b] = draws(seed, a, b - a)
+
+    _chunked(nwords, fill)
     tail = bits % 64
     if nwords and tail:
         out[-1] &= np.uint64((1 << tail) - 1)
@@ -127,16 +147,21 @@ def error_positions(seed: int, n_cw: int, r: int, p_single: float = 0.0,
     s_pos = subseed(seed, "pos")
     pos1 = np.zeros(n_cw, dtype=np.uint8)
     pos2 = np.zeros(n_cw, dtype=np.uint8)
-    for a in range(0, n_cw, _CHUNK):
-        b = min(n_cw, a + _CHUNK)
+
+    def fill(a, b):
         u = draws(s_kind, a, b - a) >> np.uint64(11)
         one = u < np.uint64(t1)
-        two = (u >= np.uint64(t1)) & (u < np.uint64(t2))
+        if t2 == 0:
+            return
         v = draws(s_pos, a, b - a)
         first = _first_position(v, n)
-        second = _second_position(v, first, n)
-        pos1[a:b] = np.where(one | two, first, 0).astype(np.uint8)
-        pos2[a:b] = np.where(two, second, 0).astype(np.uint8)
+        pos1[a:b] = np.where(u < np.uint64(t2), first, 0).astype(np.uint8)
+        if t2 > t1:
+            two = (~one) & (u < np.uint64(t2))
+            second = _second_position(v, first, n)
+            pos2[a:b] = np.where(two, second, 0).astype(np.uint8)
+
+    _chunked(n_cw, fill)
     return pos1, pos2
 
 
@@ -144,16 +169,13 @@ def flip_masks(pos1: np.ndarray, pos2: np.ndarray, r: int) -> np.ndarray:
     """Storage-layout flip masks (bit p-1 for position p) for the positions."""
     _, _, wpc = code_sizes(r)
     n_cw = pos1.size
-    masks = np.zeros((n_cw, wpc), dtype=np.uint64)
+    masks = np.zeros(n_cw * wpc, dtype=np.uint64)
     for pos in (pos1, pos2):
-        pos = pos.astype(np.int64)
-        has = pos > 0
-        bit = np.where(has, pos - 1, 0)
-        word = bit // 64
-        val = np.where(has, np.left_shift(np.uint64(1), (bit % 64).astype(np.uint64)), np.uint64(0))
-        for w in range(wpc):
-            masks[:, w] ^= np.where(word == w, val, np.uint64(0))
-    return masks.reshape(-1)
+        idx = np.flatnonzero(pos)
+        bit = pos[idx].astype(np.uint64) - np.uint64(1)
+        word = idx.astype(np.int64) * wpc + (bit >> np.uint64(6)).astype(np.int64)
+        masks[word] ^= np.left_shift(np.uint64(1), bit & np.uint64(63))
+    return masks
 
 
 def padding_garbage(seed: int, n_cw: int, r: int) -> np.ndarray:
@@ -161,9 +183,12 @@ def padding_garbage(seed: int, n_cw: int, r: int) -> np.ndarray:
     codeword, zero elsewhere.  A decoder must ignore them."""
     n, _, wpc = code_sizes(r)
     g = np.empty(n_cw * wpc, dtype=np.uint64)
-    for a in range(0, g.size, _CHUNK):
-        b = min(g.size, a + _CHUNK)
-        g[a:b] = draws(subseed(seed, "garbage"), a, b - a)
+    gseed = subseed(seed, "garbage")
+
+    def fill(a, b):
+        g[a:b] = draws(gseed, a, b - a)
+
+    _chunked(g.size, fill)
     g = g.reshape(n_cw, wpc)
     valid = [(1 << min(64, max(0, n - 64 * w))) - 1 for w in range(wpc)]
     for w in range(wpc):

@@ -1,0 +1,173 @@
+"""GPU parity of the plain decode (and the encoder) against the CPU oracle.
+
+Tolerance: 0 bits.  The arithmetic is integer GF(2) and the decoder is a
+total function with exactly one correct output per input, so the data stream
+and the error positions must be byte-identical to the oracle's.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1412_6862_amd as hm
+import synth
+from _inputs import received_words, to_device, to_host_u8
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 2, 63, 64, 65, 255, 256, 257, 1023, 1024, 1025, 4097, 20000]
+
+
+def _check(y, r, device, stream=None):
+    import torch
+
+    d_ref, e_ref = oracle.decode(y, r)
+    data, ep = hm.decode(to_device(y, device), r, stream=stream)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host_u8(data), d_ref)
+    assert np.array_equal(to_host_u8(ep), e_ref)
+
+
+@pytest.mark.parametrize("r", [3, 4, 5, 6, 7])
+@pytest.mark.parametrize("n_cw", SIZES)
+def test_plain_parity_ragged_sizes(gpu_device, r, n_cw):
+    y = received_words(synth.workload_seed("gpu-ragged", r, n_cw), n_cw, r, p_single=0.3, p_double=0.1)
+    _check(y, r, gpu_device)
+
+
+@pytest.mark.parametrize("r", [4, 5, 6])
+@pytest.mark.parametrize("p", synth.PLAIN_ERROR_RATES)
+def test_plain_parity_error_rates(gpu_device, r, p):
+    n_cw = 50000
+    y = received_words(synth.workload_seed("gpu-rates", r, str(p)), n_cw, r, p_single=p)
+    _check(y, r, gpu_device)
+
+
+def test_plain_parity_hamming127_error_mix(gpu_device):
+    # 70% clean, 25% one flip, 5% two flips (deterministic miscorrection)
+    r, n_cw = 7, 30000
+    y = received_words(synth.workload_seed("gpu-mix", r), n_cw, r, p_single=0.25, p_double=0.05)
+    _check(y, r, gpu_device)
+
+
+@pytest.mark.parametrize("r", [3, 4, 5, 6, 7])
+def test_plain_every_lane_shape_and_grid_cap(gpu_device, r):
+    old = hm.hamming_plain_config_get(r)
+    n_cw = 9000
+    y = received_words(synth.workload_seed("gpu-shapes", r), n_cw, r, p_single=0.4, p_double=0.1)
+    try:
+        for u in (2, 4, 8, 16):
+            if u * hm.hamming_message_bits(r) < 32:
+                continue
+            for cap in (0, 1, 3, 64):
+                hm.hamming_plain_config_set(r, u, cap)
+                _check(y, r, gpu_device)
+    finally:
+        hm.hamming_plain_config_set(r, *old)
+
+
+@pytest.mark.parametrize("r", [3, 6, 7])
+def test_plain_unaligned_input_and_errpos(gpu_device, r):
+    import torch
+
+    n_cw = 3000
+    wpc = hm.words_per_codeword(r)
+    y = received_words(synth.workload_seed("gpu-unaligned", r), n_cw, r, p_single=0.5)
+    d_ref, e_ref = oracle.decode(y, r)
+    big = torch.zeros(y.size + 1, dtype=torch.int64, device=gpu_device)
+    big[1:] = to_device(y, gpu_device)
+    cw = big[1:]                                   # 8-byte but not 16-byte aligned
+    assert cw.data_ptr() % 16 == 8
+    data = torch.empty(hm.hamming_data_bytes(n_cw, r), dtype=torch.uint8, device=gpu_device)
+    epbuf = torch.zeros(n_cw + 3, dtype=torch.uint8, device=gpu_device)
+    hm.hamming_decode(cw, n_cw, r, data, epbuf[1:])
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host_u8(data), d_ref)
+    ep = to_host_u8(epbuf)
+    assert np.array_equal(ep[1:n_cw + 1], e_ref)
+    assert ep[0] == 0 and not ep[n_cw + 1:].any()
+    assert wpc in (1, 2)
+
+
+@pytest.mark.parametrize("r", [3, 4, 5, 6, 7])
+def test_plain_writes_nothing_outside_outputs_and_keeps_input(gpu_device, r):
+    import torch
+
+    n_cw = 4099
+    y = received_words(synth.workload_seed("gpu-canary", r), n_cw, r, p_single=0.5)
+    d_ref, e_ref = oracle.decode(y, r)
+    nbytes = hm.hamming_data_bytes(n_cw, r)
+    canary = 4096
+    data = torch.full((nbytes + canary,), 0xA5, dtype=torch.uint8, device=gpu_device)
+    ep = torch.full((n_cw + canary,), 0x5A, dtype=torch.uint8, device=gpu_device)
+    cw = to_device(y, gpu_device)
+    before = cw.clone()
+    hm.hamming_decode(cw, n_cw, r, data, ep)
+    torch.cuda.synchronize()
+    d = to_host_u8(data)
+    e = to_host_u8(ep)
+    assert np.array_equal(d[:nbytes], d_ref) and (d[nbytes:] == 0xA5).all()
+    assert np.array_equal(e[:n_cw], e_ref) and (e[n_cw:] == 0x5A).all()
+    assert torch.equal(cw, before)
+
+
+def test_plain_empty_packet_writes_nothing(gpu_device):
+    import torch
+
+    data = torch.full((64,), 7, dtype=torch.uint8, device=gpu_device)
+    cw = torch.zeros(8, dtype=torch.int64, device=gpu_device)
+    for r in range(3, 8):
+        hm.hamming_decode(cw, 0, r, data, None)
+    torch.cuda.synchronize()
+    assert (data.cpu() == 7).all()
+
+
+def test_plain_errpos_optional(gpu_device):
+    import torch
+
+    r, n_cw = 5, 7000
+    y = received_words(synth.workload_seed("gpu-noep", r), n_cw, r, p_single=0.5)
+    d_ref, _ = oracle.decode(y, r)
+    data, ep = hm.decode(to_device(y, gpu_device), r, errpos=False)
+    torch.cuda.synchronize()
+    assert ep is None and np.array_equal(to_host_u8(data), d_ref)
+
+
+def test_plain_on_side_stream(gpu_device):
+    import torch
+
+    r, n_cw = 6, 12345
+    y = received_words(synth.workload_seed("gpu-stream", r), n_cw, r, p_single=0.5)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        _check(y, r, gpu_device, stream=s)
+
+
+# ---- full workload sizes (the bench's launch configuration) ------------------
+
+FULL = [
+    (3, 65536, 0.5, 0.0),
+    (4, 1 << 26, 0.1, 0.0),
+    (5, 1 << 26, 0.1, 0.0),
+    (6, 1 << 26, 0.1, 0.0),
+    (7, 1 << 25, 0.25, 0.05),
+]
+
+
+@pytest.mark.parametrize("r,n_cw,p1,p2", FULL)
+def test_plain_parity_full_size(gpu_device, r, n_cw, p1, p2):
+    y = received_words(synth.workload_seed("gpu-full", r), n_cw, r, p_single=p1, p_double=p2)
+    _check(y, r, gpu_device)
+
+
+# ---- encoder -------------------------------------------------------------------
+
+@pytest.mark.parametrize("r", [3, 4, 5, 6, 7])
+@pytest.mark.parametrize("n_cw", [1, 63, 64, 65, 1000, 65537])
+def test_encode_parity(gpu_device, r, n_cw):
+    import torch
+
+    stream = synth.message_stream(synth.workload_seed("gpu-enc", r, n_cw), n_cw, r)
+    ref = oracle.encode(stream, n_cw, r)
+    out = hm.encode(to_device(stream, gpu_device), n_cw, r)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint64), ref)
