@@ -1,0 +1,244 @@
+"""Throughput bench of the MI355X Hamming decoder.
+
+One step = the plain decode of one packet of 2^26 codewords for each of
+Hamming(15,11), (31,26) and (63,57) (r = 4, 5, 6), 10% single-bit error rate,
+inputs resident in HBM.  Prints one JSON line: decoded payload Gbit/s over the
+step, the HBM roofline of the dominant kernel (the r = 6 decode) measured with
+HIP events on the launch stream, and the CPU oracle timed on the host cores on
+a bounded slice of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import glob
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "decoded payload Gbit/s & %HBM roofline, batched vs plain; p50/p99 latency"
+HBM_PEAK_GBPS = 8000.0
+WORKLOAD_R = (4, 5, 6)
+WORKLOAD_LOG2 = 26
+P_SINGLE = 0.1
+DOMINANT_R = 6
+PROFILE_GLOB = os.path.join(ROOT, "profiles", "decode_plain_r6_2p26_traffic.md")
+
+
+def algorithmic_bytes_per_codeword(r: int) -> float:
+    """Codeword read + dense message write + one errpos byte."""
+    k = (1 << r) - 1 - r
+    wpc = 2 if r == 7 else 1
+    return 8.0 * wpc + k / 8.0 + 1.0
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1412_6862_amd", "csrc", "*"))):
+        with open(p, "rb") as fh:
+            h.update(os.path.basename(p).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, if it was taken from the current kernel sources."""
+    if not os.path.exists(PROFILE_GLOB):
+        return None
+    fields = {}
+    with open(PROFILE_GLOB) as fh:
+        for line in fh:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel source digest") != kernel_source_digest():
+        return None
+    try:
+        return float(fields["HBM bytes per launch (scaled)"])
+    except (KeyError, ValueError):
+        return None
+
+
+def make_packet(r: int, n_cw: int, p: float, dev):
+    """Device-resident received words: random messages encoded on the GPU by
+    the library's encoder, then flipped by the seeded channel masks."""
+    import numpy as np
+    import torch
+
+    import paper_1412_6862_amd as hm
+    import synth
+
+    seed = synth.workload_seed("bench", r, str(p))
+    msg = torch.from_numpy(synth.message_stream(seed, n_cw, r).view(np.int64)).to(dev)
+    cw = hm.encode(msg, n_cw, r)
+    p1, p2 = synth.error_positions(seed, n_cw, r, p_single=p)
+    cw ^= torch.from_numpy(synth.flip_masks(p1, p2, r).view(np.int64)).to(dev)
+    torch.cuda.synchronize()
+    del msg
+    return cw
+
+
+def cpu_baseline(log2_sample: int):
+    """The oracle on the host cores over a slice of the same workload."""
+    import oracle
+    import synth
+
+    n = 1 << log2_sample
+    threads = oracle.default_threads()
+    bits = 0
+    elapsed = 0.0
+    for r in WORKLOAD_R:
+        seed = synth.workload_seed("bench", r, str(P_SINGLE))
+        stream = synth.message_stream(seed, n, r)
+        cw = oracle.encode(stream, n, r, nthreads=threads)
+        p1, p2 = synth.error_positions(seed, n, r, p_single=P_SINGLE)
+        y = cw ^ synth.flip_masks(p1, p2, r)
+        t0 = time.perf_counter()
+        oracle.decode(y, r, nthreads=threads)
+        elapsed += time.perf_counter() - t0
+        bits += n * ((1 << r) - 1 - r)
+    return {
+        "value": round(bits / elapsed / 1e9, 3),
+        "unit": "Gbit/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": "2^%d codewords of each of r=4,5,6 (p=%.2f), %d threads, decode only, %.2f s"
+                  % (log2_sample, P_SINGLE, threads, elapsed),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--log2-cw", type=int, default=WORKLOAD_LOG2)
+    ap.add_argument("--cpu-log2", type=int, default=24)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes 5 times (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this decoder runs on one GPU; --gpus must be 1 (codewords are "
+              "independent, so more GPUs would each decode their own share)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1412_6862_amd as hm
+
+    dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration // 8, dtype=torch.int64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8, "launches": 5}), flush=True)
+        return 0
+    hm.library()
+    n_cw = 1 << args.log2_cw
+    packets = {}
+    for r in WORKLOAD_R:
+        cw = make_packet(r, n_cw, P_SINGLE, dev)
+        data = torch.empty(hm.hamming_data_bytes(n_cw, r), dtype=torch.uint8, device=dev)
+        ep = torch.empty(n_cw, dtype=torch.uint8, device=dev)
+        packets[r] = (cw, data, ep)
+    stream = torch.cuda.current_stream()
+
+    def step(events=None):
+        for r in WORKLOAD_R:
+            cw, data, ep = packets[r]
+            if events is not None:
+                events[r][0].record(stream)
+            hm.hamming_decode(cw, n_cw, r, data, ep, stream)
+            if events is not None:
+                events[r][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    evs = [{r: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for r in WORKLOAD_R} for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t_start.record(stream)
+    for i in range(args.steps):
+        step(evs[i])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_ms = t_start.elapsed_time(t_end)
+    ms_per_step = max(gpu_ms, wall * 1e3) / args.steps
+
+    per_r = []
+    for r in WORKLOAD_R:
+        times = sorted(e[r][0].elapsed_time(e[r][1]) for e in evs)
+        avg = sum(times) / len(times)
+        algo = algorithmic_bytes_per_codeword(r) * n_cw
+        k = (1 << r) - 1 - r
+        per_r.append({
+            "r": r, "n_cw": n_cw, "avg_us": round(avg * 1e3, 2),
+            "p50_us": round(times[len(times) // 2] * 1e3, 2),
+            "p99_us": round(times[min(len(times) - 1, int(0.99 * len(times)))] * 1e3, 2),
+            "algorithmic_GBps": round(algo / avg / 1e6, 1),
+            "frac_hbm": round(algo / avg / 1e6 / HBM_PEAK_GBPS, 4),
+            "payload_Gbps": round(n_cw * k / avg / 1e6, 1),
+        })
+    dom = next(x for x in per_r if x["r"] == DOMINANT_R)
+    traffic = recorded_traffic()
+    bits_per_step = sum(n_cw * ((1 << r) - 1 - r) for r in WORKLOAD_R)
+    value = bits_per_step / (ms_per_step * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Gbit/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain decode, one packet of 2^%d codewords each of Hamming(15,11), "
+                        "(31,26), (63,57); uniform random messages; %.0f%% single-bit errors at "
+                        "uniform positions" % (args.log2_cw, P_SINGLE * 100),
+            "n_cw_per_packet": n_cw, "r": list(WORKLOAD_R), "p_single": P_SINGLE,
+        },
+        "roofline": {
+            "kernel": "decode_plain_kernel<6,%d>" % hm.hamming_plain_config_get(DOMINANT_R)[0],
+            "bound": "hbm",
+            "achieved": dom["algorithmic_GBps"],
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": dom["frac_hbm"],
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": int(algorithmic_bytes_per_codeword(DOMINANT_R) * n_cw),
+            "avg_launch_us": dom["avg_us"],
+        },
+        "per_r": per_r,
+    }
+    del packets
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_log2)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
