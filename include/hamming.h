@@ -111,12 +111,212 @@ int hamming_encode(const void *data_in, uint64_t n_cw, int r,
  * knob, no effect on results).  lane_codewords is the number of consecutive
  * codewords one lane decodes: 2, 4, 8 or 16, with lane_codewords*k >= 32.
  * max_blocks caps the workgroups of one launch (waves then loop over tiles);
- * 0 launches one wave per tile.  The shape is process-wide state read at each
+ * 0 launches one wave per tile.  xcd_chunk (1..2^20) is the number of
+ * consecutive workgroups each of the 8 XCDs takes in turn (1 = the hardware's
+ * round-robin order).  The shape is process-wide state read at each
  * hamming_decode call; set it before decoding.  Returns HAMMING_OK,
  * HAMMING_EINVAL or HAMMING_ERANGE.
  */
-int hamming_plain_config_set(int r, int lane_codewords, uint64_t max_blocks);
-int hamming_plain_config_get(int r, int *lane_codewords, uint64_t *max_blocks);
+int hamming_plain_config_set(int r, int lane_codewords, uint64_t max_blocks, uint32_t xcd_chunk);
+int hamming_plain_config_get(int r, int *lane_codewords, uint64_t *max_blocks, uint32_t *xcd_chunk);
+
+/* ---- batched decode ------------------------------------------------------ */
+
+/*
+ * One packet of a batch (40 bytes).  The batched decode applies exactly the
+ * plain decode to every packet, so each packet's outputs are byte-identical
+ * to a hamming_decode call on that packet alone.
+ *   in_word_off   : first 64-bit word of the packet's codewords in cw_arena.
+ *   n_cw          : codewords in the packet; 0 is allowed (nothing written).
+ *   r             : 3..7.
+ *   flags         : reserved, must be 0.
+ *   data_word_off : first 64-bit word of the packet's message stream in
+ *                   data_arena; hamming_data_bytes(n_cw, r)/8 words are written.
+ *   errpos_off    : first byte of the packet's n_cw errpos bytes in
+ *                   errpos_arena, or HAMMING_NO_ERRPOS.
+ * Output ranges of different packets must not overlap (hamming_batch_layout
+ * produces disjoint ones); input ranges may.
+ */
+typedef struct hamming_packet {
+    uint64_t in_word_off;
+    uint64_t n_cw;
+    uint32_t r;
+    uint32_t flags;
+    uint64_t data_word_off;
+    uint64_t errpos_off;
+} hamming_packet;
+
+#define HAMMING_NO_ERRPOS UINT64_MAX
+#define HAMMING_MAX_BATCH (1u << 24)
+
+/*
+ * Host helper: fill data_word_off and errpos_off of n descriptors (host
+ * memory) with disjoint, consecutive ranges in packet order, each rounded up to
+ * 16 bytes; in_word_off, n_cw and r are read, not changed.  Writes the arena
+ * sizes the batch needs to *data_words (64-bit words) and *errpos_bytes.
+ * Returns HAMMING_OK, HAMMING_EINVAL (NULL pointer, bad r or flags) or
+ * HAMMING_ERANGE (n above HAMMING_MAX_BATCH or n_cw too large); on error no
+ * descriptor is changed.
+ */
+int hamming_batch_layout(hamming_packet *descs, uint32_t n, uint64_t *data_words,
+                         uint64_t *errpos_bytes);
+
+/* Device workspace bytes hamming_decode_batch needs for max_packets packets
+ * (tile prefix sums and the tile-to-packet map); 0 if max_packets >
+ * HAMMING_MAX_BATCH. */
+uint64_t hamming_batch_workspace_bytes(uint32_t max_packets);
+
+/*
+ * Batched decode: decode every packet of a device-resident descriptor array.
+ * A planning kernel validates each descriptor, writes its status and computes
+ * a prefix sum of tiles (64-codeword multiples aligned to each packet's
+ * start); two more kernels build tile-to-packet maps; the decode kernel then
+ * gives one tile to each wave in global tile order, so packets of any size and
+ * r share the GPU as one stream of work.  On a non-NULL stream that is not
+ * already capturing, the four kernels are captured once into a hipGraph
+ * (cached per argument set) and replayed on later calls; the number of packets
+ * is read on the device, so one graph serves every batch of up to max_packets
+ * packets in the same arenas.
+ *   cw_arena, cw_words     : device codeword arena and its size in 64-bit words.
+ *   descs                  : device, max_packets descriptors, 8-byte aligned.
+ *   n_packets_dev          : device uint32, packets to decode this call
+ *                            (values above max_packets are clamped).
+ *   max_codewords          : an upper bound on the total codewords of any batch
+ *                            decoded with these arguments, used only to size the
+ *                            grid; 0 derives one from cw_words (exact when
+ *                            packets do not share input words).  Any value is
+ *                            correct; a low one is slower, a high one launches
+ *                            idle waves.
+ *   data_arena, data_words : device message arena, 8-byte aligned, and its size.
+ *   errpos_arena, errpos_bytes : device errpos arena and size (may be NULL/0
+ *                            when every packet uses HAMMING_NO_ERRPOS).
+ *   status_out             : device int32[max_packets] or NULL; per packet
+ *                            HAMMING_OK, HAMMING_EINVAL (bad r or flags) or
+ *                            HAMMING_ERANGE (a range outside its arena).  A
+ *                            rejected packet is skipped; the others decode as
+ *                            usual.
+ *   workspace, workspace_bytes : device scratch, 8-byte aligned, at least
+ *                            hamming_batch_workspace_bytes(max_packets); owned
+ *                            by the caller, not shared by concurrent calls.
+ * Returns HAMMING_OK, HAMMING_EINVAL, HAMMING_EALIGN, HAMMING_ERANGE,
+ * HAMMING_ENOMEM (workspace too small) or HAMMING_EDEVICE.
+ */
+int hamming_decode_batch(const uint64_t *cw_arena, uint64_t cw_words,
+                         const hamming_packet *descs, const uint32_t *n_packets_dev,
+                         uint32_t max_packets, uint64_t max_codewords, uint64_t *data_arena,
+                         uint64_t data_words, uint8_t *errpos_arena, uint64_t errpos_bytes,
+                         int32_t *status_out, void *workspace, uint64_t workspace_bytes,
+                         hipStream_t stream);
+
+/*
+ * Launch shape of the batched decode (a tuning knob, no effect on results):
+ * schedule selects the per-r lane widths (0 or 1); xcd_chunk (1..2^20) the
+ * consecutive workgroups each of the 8 XCDs takes in turn (1 = hardware
+ * order); grid_cap_blocks caps the decode kernel's workgroups (0 = no cap;
+ * waves then loop over tiles); use_graph whether to capture and replay a
+ * hipGraph (1) or launch directly (0).  Process-wide; set before decoding.
+ * Returns HAMMING_OK or HAMMING_EINVAL.
+ */
+int hamming_batch_config_set(int schedule, uint32_t xcd_chunk, uint32_t grid_cap_blocks, int use_graph);
+int hamming_batch_config_get(int *schedule, uint32_t *xcd_chunk, uint32_t *grid_cap_blocks, int *use_graph);
+
+/* ---- serving: continuous batching of decode requests ---------------------- */
+
+/*
+ * A server decodes requests (one packet each) taken from a device-resident
+ * codeword pool, batching whatever is waiting into one hamming_decode_batch
+ * launch as soon as one of its in-flight batch slots is free, so requests that
+ * arrive while earlier batches run are admitted and overlap with them on the
+ * device.  A request is admitted when its outputs fit in the server's output
+ * pool (the device-memory admission cap); until then it waits in FIFO order.
+ * The server is driven by the caller (hamming_server_progress) and keeps no
+ * thread of its own; one server must not be used from two threads at once.
+ * The arithmetic of every request is exactly the plain decode's.
+ */
+typedef struct hamming_server hamming_server;
+
+typedef struct hamming_server_config {
+    uint32_t slots;               /* batches in flight, each on its own stream (1..16) */
+    uint32_t max_batch_packets;   /* requests per batch (1..65536) */
+    uint64_t max_batch_codewords; /* a batch closes once it holds this many codewords (>= 1) */
+    uint32_t max_queue;           /* requests waiting for admission (submit fails beyond) */
+    uint32_t auto_release;        /* 1: free a request's outputs once its completion is recorded */
+} hamming_server_config;
+
+typedef struct hamming_completion {
+    uint64_t request_id;
+    uint64_t data_offset;         /* byte offset of the message stream in the output pool */
+    uint64_t errpos_offset;       /* byte offset of the errpos bytes in the output pool */
+    uint64_t submit_ns;           /* arrival time given to hamming_server_submit */
+    uint64_t complete_ns;         /* time the server observed the batch complete */
+    int32_t status;               /* HAMMING_OK or the descriptor's error status */
+    uint32_t reserved;
+} hamming_completion;
+
+/* Monotonic clock (nanoseconds) used for arrival and completion times. */
+uint64_t hamming_server_now_ns(void);
+
+/*
+ * Create a server on the current device.  cw_pool/cw_pool_words is the
+ * device codeword pool requests point into (read only); output_pool /
+ * output_pool_bytes (device, 256-byte aligned) is where results are written,
+ * and its size is the admission cap.  Both stay owned by the caller and must
+ * outlive the server.  The server allocates per-slot streams, descriptor
+ * arrays, pinned staging and workspaces; hamming_server_destroy frees them.
+ * Returns HAMMING_OK, HAMMING_EINVAL (bad config, NULL pointer),
+ * HAMMING_EALIGN, HAMMING_ENOMEM or HAMMING_EDEVICE.
+ */
+int hamming_server_create(const hamming_server_config *config, const uint64_t *cw_pool,
+                          uint64_t cw_pool_words, void *output_pool, uint64_t output_pool_bytes,
+                          hamming_server **out);
+
+/* Wait for every batch in flight, then free everything the server owns.
+ * Returns HAMMING_OK or HAMMING_EINVAL (NULL). */
+int hamming_server_destroy(hamming_server *server);
+
+/*
+ * Queue a request: n_cw codewords of code r starting at word in_word_off of
+ * the pool, arriving at arrival_ns (hamming_server_now_ns() time base).  On
+ * success *request_id receives the request's id (ids count up from 0).  Does
+ * not launch anything.  Returns HAMMING_OK, HAMMING_EINVAL (bad r, NULL),
+ * HAMMING_ERANGE (outside the pool, or outputs larger than the whole output
+ * pool) or HAMMING_ENOMEM (queue full).
+ */
+int hamming_server_submit(hamming_server *server, uint64_t in_word_off, uint64_t n_cw, uint32_t r,
+                          uint64_t arrival_ns, uint64_t *request_id);
+
+/*
+ * Non-blocking step: record completions of finished batches (freeing outputs
+ * when auto_release is set), admit waiting requests in FIFO order while their
+ * outputs fit, and launch one batch per free slot.  Returns HAMMING_OK or
+ * HAMMING_EDEVICE.
+ */
+int hamming_server_progress(hamming_server *server);
+
+/* Move up to max recorded completions into out[]; *n_out receives the count. */
+int hamming_server_poll(hamming_server *server, hamming_completion *out, uint32_t max, uint32_t *n_out);
+
+/* Free the outputs of a completed request (when auto_release is 0).  Returns
+ * HAMMING_OK or HAMMING_EINVAL (unknown or unfinished request). */
+int hamming_server_release(hamming_server *server, uint64_t request_id);
+
+/* Device base address and size of the output pool. */
+int hamming_server_output_pool(hamming_server *server, void **base, uint64_t *bytes);
+
+/* Requests queued, requests in flight, output bytes in use, batches launched. */
+int hamming_server_stats(hamming_server *server, uint64_t *queued, uint64_t *inflight,
+                         uint64_t *output_bytes_used, uint64_t *batches);
+
+/*
+ * Open-loop load generator: submit n requests at times start + arrival_ns[i]
+ * (start = now), driving progress between arrivals, until all complete or
+ * timeout_ns passes.  latency_ns[i] receives completion - scheduled arrival,
+ * *elapsed_ns the wall time of the run.  Needs auto_release = 1.  Returns
+ * HAMMING_OK, HAMMING_EINVAL, HAMMING_ERANGE (timeout) or a submit error.
+ */
+int hamming_server_run_trace(hamming_server *server, uint32_t n, const uint64_t *arrival_ns,
+                             const uint64_t *in_word_off, const uint64_t *n_cw, const uint32_t *r,
+                             uint64_t timeout_ns, uint64_t *latency_ns, uint64_t *elapsed_ns);
 
 /* Static, human-readable text for a status code. */
 const char *hamming_strerror(int status);

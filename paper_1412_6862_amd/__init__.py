@@ -43,10 +43,58 @@ _SIGNATURES = {
     "hamming_data_bytes": ([_u64, _i32], _u64),
     "hamming_decode": ([_vp, _u64, _i32, _vp, _vp, _vp], _i32),
     "hamming_encode": ([_vp, _u64, _i32, _vp, _vp], _i32),
-    "hamming_plain_config_set": ([_i32, _i32, _u64], _i32),
-    "hamming_plain_config_get": ([_i32, ctypes.POINTER(_i32), ctypes.POINTER(_u64)], _i32),
+    "hamming_plain_config_set": ([_i32, _i32, _u64, ctypes.c_uint32], _i32),
+    "hamming_plain_config_get": ([_i32, ctypes.POINTER(_i32), ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_uint32)],
+                                 _i32),
     "hamming_strerror": ([_i32], ctypes.c_char_p),
+    "hamming_batch_layout": ([_vp, ctypes.c_uint32, ctypes.POINTER(_u64), ctypes.POINTER(_u64)], _i32),
+    "hamming_batch_workspace_bytes": ([ctypes.c_uint32], _u64),
+    "hamming_decode_batch": ([_vp, _u64, _vp, _vp, ctypes.c_uint32, _u64, _vp, _u64, _vp, _u64, _vp, _vp, _u64,
+                              _vp], _i32),
+    "hamming_batch_config_set": ([_i32, ctypes.c_uint32, ctypes.c_uint32, _i32], _i32),
+    "hamming_batch_config_get": ([ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_uint32),
+                                  ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_i32)], _i32),
 }
+
+class hamming_server_config(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_uint32), ("max_batch_packets", ctypes.c_uint32),
+                ("max_batch_codewords", ctypes.c_uint64), ("max_queue", ctypes.c_uint32),
+                ("auto_release", ctypes.c_uint32)]
+
+
+class hamming_completion(ctypes.Structure):
+    _fields_ = [("request_id", ctypes.c_uint64), ("data_offset", ctypes.c_uint64),
+                ("errpos_offset", ctypes.c_uint64), ("submit_ns", ctypes.c_uint64),
+                ("complete_ns", ctypes.c_uint64), ("status", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
+
+
+_SIGNATURES.update({
+    "hamming_server_now_ns": ([], _u64),
+    "hamming_server_create": ([ctypes.POINTER(hamming_server_config), _vp, _u64, _vp, _u64, ctypes.POINTER(_vp)],
+                              _i32),
+    "hamming_server_destroy": ([_vp], _i32),
+    "hamming_server_submit": ([_vp, _u64, _u64, ctypes.c_uint32, _u64, ctypes.POINTER(_u64)], _i32),
+    "hamming_server_progress": ([_vp], _i32),
+    "hamming_server_poll": ([_vp, ctypes.POINTER(hamming_completion), ctypes.c_uint32,
+                             ctypes.POINTER(ctypes.c_uint32)], _i32),
+    "hamming_server_release": ([_vp, _u64], _i32),
+    "hamming_server_output_pool": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_u64)], _i32),
+    "hamming_server_stats": ([_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64),
+                              ctypes.POINTER(_u64)], _i32),
+    "hamming_server_run_trace": ([_vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _u64, _vp, ctypes.POINTER(_u64)],
+                                 _i32),
+})
+
+HAMMING_NO_ERRPOS = (1 << 64) - 1
+HAMMING_MAX_BATCH = 1 << 24
+
+
+def packet_dtype():
+    """numpy dtype of ``hamming_packet`` (40 bytes, the C struct's layout)."""
+    import numpy as np
+
+    return np.dtype([("in_word_off", "<u8"), ("n_cw", "<u8"), ("r", "<u4"), ("flags", "<u4"),
+                     ("data_word_off", "<u8"), ("errpos_off", "<u8")])
 
 
 def library() -> ctypes.CDLL:
@@ -117,15 +165,60 @@ def hamming_encode(data_in, n_cw: int, r: int, codewords_out, stream=None) -> No
            "hamming_encode")
 
 
-def hamming_plain_config_set(r: int, lane_codewords: int, max_blocks: int = 0) -> None:
-    _check(library().hamming_plain_config_set(r, lane_codewords, max_blocks), "hamming_plain_config_set")
+def hamming_plain_config_set(r: int, lane_codewords: int, max_blocks: int = 0, xcd_chunk: int = 1) -> None:
+    _check(library().hamming_plain_config_set(r, lane_codewords, max_blocks, xcd_chunk), "hamming_plain_config_set")
 
 
-def hamming_plain_config_get(r: int) -> tuple[int, int]:
+def hamming_plain_config_get(r: int) -> tuple[int, int, int]:
     u = ctypes.c_int()
     mb = ctypes.c_uint64()
-    _check(library().hamming_plain_config_get(r, ctypes.byref(u), ctypes.byref(mb)), "hamming_plain_config_get")
-    return u.value, mb.value
+    xc = ctypes.c_uint32()
+    _check(library().hamming_plain_config_get(r, ctypes.byref(u), ctypes.byref(mb), ctypes.byref(xc)),
+           "hamming_plain_config_get")
+    return u.value, mb.value, xc.value
+
+
+def hamming_batch_layout(descs) -> tuple[int, int]:
+    """Fill data_word_off / errpos_off of a host numpy array of packets in place;
+    returns (data_words, errpos_bytes)."""
+    import numpy as np
+
+    if descs.dtype != packet_dtype() or not descs.flags["C_CONTIGUOUS"]:
+        raise ValueError("descs must be a contiguous array of packet_dtype()")
+    dw = ctypes.c_uint64()
+    eb = ctypes.c_uint64()
+    _check(library().hamming_batch_layout(descs.ctypes.data if descs.size else None, descs.size,
+                                          ctypes.byref(dw), ctypes.byref(eb)), "hamming_batch_layout")
+    assert isinstance(descs, np.ndarray)
+    return dw.value, eb.value
+
+
+def hamming_batch_workspace_bytes(max_packets: int) -> int:
+    return int(library().hamming_batch_workspace_bytes(max_packets))
+
+
+def hamming_decode_batch(cw_arena, cw_words: int, descs, n_packets_dev, max_packets: int, max_codewords: int,
+                         data_arena, data_words: int, errpos_arena, errpos_bytes: int, status_out, workspace,
+                         workspace_bytes: int, stream=None) -> None:
+    """Enqueue ``hamming_decode_batch`` (device tensors or raw pointers)."""
+    _check(library().hamming_decode_batch(_ptr(cw_arena), cw_words, _ptr(descs), _ptr(n_packets_dev),
+                                          max_packets, max_codewords, _ptr(data_arena), data_words,
+                                          _ptr(errpos_arena),
+                                          errpos_bytes, _ptr(status_out), _ptr(workspace), workspace_bytes,
+                                          _stream(stream)), "hamming_decode_batch")
+
+
+def hamming_batch_config_set(schedule: int, xcd_chunk: int = 1, grid_cap_blocks: int = 0,
+                             use_graph: int = 1) -> None:
+    _check(library().hamming_batch_config_set(schedule, xcd_chunk, grid_cap_blocks, use_graph),
+           "hamming_batch_config_set")
+
+
+def hamming_batch_config_get() -> tuple[int, int, int, int]:
+    s, rt, b, g = ctypes.c_int(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_int()
+    _check(library().hamming_batch_config_get(ctypes.byref(s), ctypes.byref(rt), ctypes.byref(b), ctypes.byref(g)),
+           "hamming_batch_config_get")
+    return s.value, rt.value, b.value, g.value
 
 
 # ---- conveniences over torch tensors --------------------------------------------
@@ -167,3 +260,179 @@ def encode(messages, n_cw: int, r: int, stream=None):
     out = torch.empty(n_cw * words_per_codeword(r), dtype=torch.int64, device=messages.device)
     hamming_encode(messages.contiguous(), n_cw, r, out, stream)
     return out
+
+
+class BatchDecoder:
+    """Device-resident batch: descriptor array, packet count, outputs and
+    workspace for up to ``max_packets`` packets over one codeword arena.
+
+    ``set_packets`` lays out a host descriptor array, uploads it and sizes the
+    output arenas; ``decode`` enqueues one ``hamming_decode_batch``.
+    """
+
+    def __init__(self, cw_arena, max_packets: int, device=None):
+        import torch
+
+        self.device = device or cw_arena.device
+        self.cw_arena = cw_arena
+        self.max_packets = max_packets
+        self.ws_bytes = hamming_batch_workspace_bytes(max_packets)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.descs_dev = torch.zeros(max_packets * 40, dtype=torch.uint8, device=self.device)
+        self.n_dev = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.status = torch.zeros(max_packets, dtype=torch.int32, device=self.device)
+        self.data = None
+        self.errpos = None
+        self.descs = None
+
+    def set_packets(self, descs, layout: bool = True, data_words=None, errpos_bytes=None):
+        import numpy as np
+        import torch
+
+        if descs.size > self.max_packets:
+            raise ValueError("more packets than max_packets")
+        if layout:
+            data_words, errpos_bytes = hamming_batch_layout(descs)
+        self.descs = descs
+        raw = torch.from_numpy(np.ascontiguousarray(descs).view(np.uint8).copy())
+        self.descs_dev[: raw.numel()].copy_(raw.to(self.device))
+        self.n_dev.fill_(int(descs.size))
+        if self.data is None or self.data.numel() < max(1, data_words):
+            self.data = torch.empty(max(1, data_words), dtype=torch.int64, device=self.device)
+        if self.errpos is None or self.errpos.numel() < max(1, errpos_bytes):
+            self.errpos = torch.empty(max(1, errpos_bytes), dtype=torch.uint8, device=self.device)
+        self.data_words = data_words
+        self.errpos_bytes = errpos_bytes
+
+    def decode(self, stream=None, max_codewords: int = 0):
+        hamming_decode_batch(self.cw_arena, self.cw_arena.numel(), self.descs_dev, self.n_dev, self.max_packets,
+                             max_codewords, self.data, self.data.numel(), self.errpos, self.errpos.numel(), self.status,
+                             self.workspace, self.ws_bytes, stream)
+
+
+# ---- serving -------------------------------------------------------------------
+
+def hamming_server_now_ns() -> int:
+    return int(library().hamming_server_now_ns())
+
+
+def hamming_server_create(config: hamming_server_config, cw_pool, cw_pool_words: int, output_pool,
+                          output_pool_bytes: int) -> int:
+    h = ctypes.c_void_p()
+    _check(library().hamming_server_create(ctypes.byref(config), _ptr(cw_pool), cw_pool_words, _ptr(output_pool),
+                                           output_pool_bytes, ctypes.byref(h)), "hamming_server_create")
+    return h.value
+
+
+def hamming_server_destroy(server: int) -> None:
+    _check(library().hamming_server_destroy(server), "hamming_server_destroy")
+
+
+def hamming_server_submit(server: int, in_word_off: int, n_cw: int, r: int, arrival_ns: int) -> int:
+    rid = ctypes.c_uint64()
+    _check(library().hamming_server_submit(server, in_word_off, n_cw, r, arrival_ns, ctypes.byref(rid)),
+           "hamming_server_submit")
+    return rid.value
+
+
+def hamming_server_progress(server: int) -> None:
+    _check(library().hamming_server_progress(server), "hamming_server_progress")
+
+
+def hamming_server_poll(server: int, max_n: int = 1024) -> list:
+    buf = (hamming_completion * max_n)()
+    n = ctypes.c_uint32()
+    _check(library().hamming_server_poll(server, buf, max_n, ctypes.byref(n)), "hamming_server_poll")
+    return [buf[i] for i in range(n.value)]
+
+
+def hamming_server_release(server: int, request_id: int) -> None:
+    _check(library().hamming_server_release(server, request_id), "hamming_server_release")
+
+
+def hamming_server_output_pool(server: int) -> tuple[int, int]:
+    base = ctypes.c_void_p()
+    nbytes = ctypes.c_uint64()
+    _check(library().hamming_server_output_pool(server, ctypes.byref(base), ctypes.byref(nbytes)),
+           "hamming_server_output_pool")
+    return base.value, nbytes.value
+
+
+def hamming_server_stats(server: int) -> dict:
+    q, f, u, b = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(library().hamming_server_stats(server, ctypes.byref(q), ctypes.byref(f), ctypes.byref(u), ctypes.byref(b)),
+           "hamming_server_stats")
+    return {"queued": q.value, "inflight": f.value, "output_bytes_used": u.value, "batches": b.value}
+
+
+def hamming_server_run_trace(server: int, arrival_ns, in_word_off, n_cw, r, timeout_ns: int):
+    """Run an open-loop trace (numpy arrays); returns (latency_ns array, elapsed_ns)."""
+    import numpy as np
+
+    a = np.ascontiguousarray(arrival_ns, dtype=np.uint64)
+    o = np.ascontiguousarray(in_word_off, dtype=np.uint64)
+    c = np.ascontiguousarray(n_cw, dtype=np.uint64)
+    rr = np.ascontiguousarray(r, dtype=np.uint32)
+    lat = np.zeros(a.size, dtype=np.uint64)
+    el = ctypes.c_uint64()
+    _check(library().hamming_server_run_trace(server, a.size, a.ctypes.data, o.ctypes.data, c.ctypes.data,
+                                              rr.ctypes.data, timeout_ns, lat.ctypes.data, ctypes.byref(el)),
+           "hamming_server_run_trace")
+    return lat, el.value
+
+
+class Server:
+    """Continuous-batching decode server over a device codeword pool."""
+
+    def __init__(self, cw_pool, slots: int = 4, max_batch_packets: int = 1024,
+                 max_batch_codewords: int = 1 << 24, output_pool_bytes: int = 1 << 30,
+                 max_queue: int = 1 << 20, auto_release: bool = False):
+        import torch
+
+        self.handle = None
+        self.pool = cw_pool
+        self.output = torch.empty(max(256, output_pool_bytes // 256 * 256), dtype=torch.uint8,
+                                  device=cw_pool.device)
+        cfg = hamming_server_config(slots, max_batch_packets, max_batch_codewords, max_queue,
+                                    1 if auto_release else 0)
+        torch.cuda.synchronize()
+        self.handle = hamming_server_create(cfg, cw_pool, cw_pool.numel(), self.output, self.output.numel())
+
+    def result(self, completion, r: int, n_cw: int):
+        """(data, errpos) device views of a completed request's outputs."""
+        nbytes = hamming_data_bytes(n_cw, r)
+        return (self.output[completion.data_offset:completion.data_offset + nbytes],
+                self.output[completion.errpos_offset:completion.errpos_offset + n_cw])
+
+    def submit(self, in_word_off: int, n_cw: int, r: int, arrival_ns: int | None = None) -> int:
+        return hamming_server_submit(self.handle, in_word_off, n_cw, r,
+                                     hamming_server_now_ns() if arrival_ns is None else arrival_ns)
+
+    def progress(self) -> None:
+        hamming_server_progress(self.handle)
+
+    def poll(self, max_n: int = 1024) -> list:
+        return hamming_server_poll(self.handle, max_n)
+
+    def release(self, request_id: int) -> None:
+        hamming_server_release(self.handle, request_id)
+
+    def output_pool(self) -> tuple[int, int]:
+        return hamming_server_output_pool(self.handle)
+
+    def stats(self) -> dict:
+        return hamming_server_stats(self.handle)
+
+    def run_trace(self, arrival_ns, in_word_off, n_cw, r, timeout_s: float = 60.0):
+        return hamming_server_run_trace(self.handle, arrival_ns, in_word_off, n_cw, r, int(timeout_s * 1e9))
+
+    def close(self) -> None:
+        if self.handle:
+            hamming_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

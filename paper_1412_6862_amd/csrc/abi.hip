@@ -19,9 +19,10 @@ using hm::DecodeLaunch;
 struct PlainShape {
     std::atomic<int> u;
     std::atomic<uint64_t> max_blocks;
+    std::atomic<uint32_t> xcd_chunk;
 };
 
-PlainShape g_plain[5] = {{8, 0}, {4, 0}, {4, 0}, {4, 0}, {2, 0}};
+PlainShape g_plain[5] = {{8, 0, 1}, {8, 0, 1}, {8, 0, 1}, {8, 0, 1}, {2, 0, 1}};
 
 bool valid_r(int r) { return r >= 3 && r <= 7; }
 
@@ -62,6 +63,7 @@ int hamming_decode(const uint64_t* codewords, uint64_t n_cw, int r, void* data_o
     L.data_words = hamming_data_bytes(n_cw, r) / 8;
     L.errpos = errpos_out;
     L.max_blocks = g_plain[r - 3].max_blocks.load(std::memory_order_relaxed);
+    L.xcd_chunk = g_plain[r - 3].xcd_chunk.load(std::memory_order_relaxed);
     return map_hip(hm::launch_decode(L, stream));
 }
 
@@ -77,20 +79,22 @@ int hamming_encode(const void* data_in, uint64_t n_cw, int r, uint64_t* codeword
     return map_hip(hm::launch_encode(r, data_in, n_cw, codewords_out, stream));
 }
 
-int hamming_plain_config_set(int r, int lane_codewords, uint64_t max_blocks)
+int hamming_plain_config_set(int r, int lane_codewords, uint64_t max_blocks, uint32_t xcd_chunk)
 {
-    if (!valid_r(r) || !hm::valid_u(r, lane_codewords)) return HAMMING_EINVAL;
-    if (max_blocks > (uint64_t(1) << 31)) return HAMMING_ERANGE;
+    if (!valid_r(r) || !hm::valid_u(r, lane_codewords) || xcd_chunk < 1) return HAMMING_EINVAL;
+    if (max_blocks > (uint64_t(1) << 31) || xcd_chunk > (1u << 20)) return HAMMING_ERANGE;
     g_plain[r - 3].u.store(lane_codewords, std::memory_order_relaxed);
     g_plain[r - 3].max_blocks.store(max_blocks, std::memory_order_relaxed);
+    g_plain[r - 3].xcd_chunk.store(xcd_chunk, std::memory_order_relaxed);
     return HAMMING_OK;
 }
 
-int hamming_plain_config_get(int r, int* lane_codewords, uint64_t* max_blocks)
+int hamming_plain_config_get(int r, int* lane_codewords, uint64_t* max_blocks, uint32_t* xcd_chunk)
 {
-    if (!valid_r(r) || !lane_codewords || !max_blocks) return HAMMING_EINVAL;
+    if (!valid_r(r) || !lane_codewords || !max_blocks || !xcd_chunk) return HAMMING_EINVAL;
     *lane_codewords = g_plain[r - 3].u.load(std::memory_order_relaxed);
     *max_blocks = g_plain[r - 3].max_blocks.load(std::memory_order_relaxed);
+    *xcd_chunk = g_plain[r - 3].xcd_chunk.load(std::memory_order_relaxed);
     return HAMMING_OK;
 }
 

@@ -1,0 +1,70 @@
+// Internal interface of the batched decode (kernels in decode_batch.hip,
+// host side in batch_host.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hamming.h"
+
+namespace hm {
+
+// Head of the caller's workspace.  After it: tile_start[max_packets + 1]
+// (uint64, exclusive prefix sum of tiles per packet), coarse[coarse_cap] and
+// fine[fine_cap] (uint32): coarse[j] is the packet holding tile j << coarse_log2,
+// fine[j] the packet holding tile j << fine_log2.
+struct BatchWs {
+    uint64_t total_tiles;   // tiles of the whole batch
+    uint64_t n_packets;     // packets planned (clamped to max_packets)
+    uint32_t coarse_log2;
+    uint32_t fine_log2;
+    uint64_t n_coarse;      // valid coarse entries
+    uint64_t n_fine;        // valid fine entries
+    uint64_t reserved[3];
+};
+
+struct BatchArgs {
+    const uint64_t* cw_arena;
+    uint64_t cw_words;
+    const hamming_packet* descs;
+    const uint32_t* n_packets_dev;
+    uint32_t max_packets;
+    uint32_t xcd_chunk;      // blocks per XCD slice of the decode grid
+    uint64_t* data_arena;
+    uint64_t data_words;
+    uint8_t* errpos_arena;
+    uint64_t errpos_bytes;
+    int32_t* status_out;
+    BatchWs* ws;
+    uint64_t* tile_start;
+    uint32_t* coarse;
+    uint32_t* fine;
+    uint32_t coarse_cap;
+    uint32_t fine_cap;
+};
+
+inline uint32_t batch_coarse_capacity(uint32_t max_packets) { return 2 * max_packets + 1024; }
+inline uint32_t batch_fine_capacity(uint32_t max_packets)
+{
+    return (4 * max_packets > (1u << 22)) ? 4 * max_packets : (1u << 22);
+}
+
+
+inline uint64_t batch_workspace_bytes(uint32_t max_packets)
+{
+    const uint64_t b = sizeof(BatchWs) + 8ull * (uint64_t(max_packets) + 1) +
+                       4ull * batch_coarse_capacity(max_packets) + 4ull * batch_fine_capacity(max_packets);
+    return (b + 255) & ~uint64_t(255);
+}
+
+// Smallest codeword count of one tile over every r and schedule; sizes the
+// grid from an upper bound on the batch's codewords.
+constexpr uint64_t kMinTileCodewords = 128;
+// Smallest input words of one tile over every r and schedule.
+constexpr uint64_t kMinTileWords = 256;
+// Waves per workgroup of the decode kernels (tile.h's kWavesPerBlock).
+constexpr uint64_t kWavesPerBlockHost = 4;
+
+hipError_t launch_batch(const BatchArgs& a, int schedule, uint32_t grid, hipStream_t stream);
+
+}  // namespace hm

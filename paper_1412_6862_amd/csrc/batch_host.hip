@@ -1,0 +1,199 @@
+// Host side of the batched decode: argument validation, the persistent grid
+// size, the hipGraph cache and hamming_batch_layout.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <atomic>
+#include <mutex>
+#include <vector>
+
+#include "batch.h"
+#include "hamming.h"
+
+namespace {
+
+using hm::BatchArgs;
+
+std::atomic<int> g_schedule{0};
+std::atomic<uint32_t> g_grid_cap{0};
+std::atomic<uint32_t> g_xcd_chunk{1};
+std::atomic<int> g_use_graph{1};
+
+// Upper bound on grid size (blocks of four waves).
+constexpr uint64_t kMaxGridBlocks = (uint64_t(1) << 31) - 1;
+
+struct GraphKey {
+    BatchArgs a;
+    int schedule;
+    uint32_t grid;
+    hipStream_t stream;
+    int device;
+    bool operator==(const GraphKey& o) const { return memcmp(this, &o, sizeof(GraphKey)) == 0; }
+};
+
+struct GraphEntry {
+    GraphKey key;
+    hipGraphExec_t exec;
+};
+
+// Executable graphs are kept until the process ends; once the cache is full,
+// calls with new argument sets launch directly.
+constexpr size_t kMaxGraphs = 64;
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;
+
+hipGraphExec_t find_or_capture(const GraphKey& key, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    for (const auto& e : g_graphs)
+        if (e.key == key) return e.exec;
+    if (g_graphs.size() >= kMaxGraphs) return nullptr;
+    if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    const hipError_t le = hm::launch_batch(key.a, key.schedule, key.grid, stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(stream, &graph);
+    if (le != hipSuccess || ce != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess || !exec) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    GraphEntry ent;
+    memset(&ent, 0, sizeof ent);
+    ent.key = key;
+    ent.exec = exec;
+    g_graphs.push_back(ent);
+    return exec;
+}
+
+bool misaligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) != 0; }
+
+}  // namespace
+
+extern "C" {
+
+uint64_t hamming_batch_workspace_bytes(uint32_t max_packets)
+{
+    if (max_packets > HAMMING_MAX_BATCH) return 0;
+    return hm::batch_workspace_bytes(max_packets);
+}
+
+int hamming_batch_layout(hamming_packet* descs, uint32_t n, uint64_t* data_words, uint64_t* errpos_bytes)
+{
+    if (n > HAMMING_MAX_BATCH) return HAMMING_ERANGE;
+    if ((n && !descs) || !data_words || !errpos_bytes) return HAMMING_EINVAL;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (descs[i].r < 3 || descs[i].r > 7 || descs[i].flags != 0) return HAMMING_EINVAL;
+        if (descs[i].n_cw > HAMMING_MAX_CODEWORDS) return HAMMING_ERANGE;
+    }
+    uint64_t dw = 0, eb = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t k = (uint64_t(1) << descs[i].r) - 1 - descs[i].r;
+        const uint64_t words = (descs[i].n_cw * k + 63) / 64;
+        descs[i].data_word_off = dw;
+        descs[i].errpos_off = eb;
+        dw += (words + 1) & ~uint64_t(1);
+        eb += (descs[i].n_cw + 15) & ~uint64_t(15);
+    }
+    *data_words = dw;
+    *errpos_bytes = eb;
+    return HAMMING_OK;
+}
+
+int hamming_batch_config_set(int schedule, uint32_t xcd_chunk, uint32_t grid_cap_blocks, int use_graph)
+{
+    if (schedule < 0 || schedule > 1 || xcd_chunk < 1 || xcd_chunk > (1u << 20) ||
+        (use_graph != 0 && use_graph != 1))
+        return HAMMING_EINVAL;
+    g_schedule.store(schedule);
+    g_xcd_chunk.store(xcd_chunk);
+    g_grid_cap.store(grid_cap_blocks);
+    g_use_graph.store(use_graph);
+    return HAMMING_OK;
+}
+
+int hamming_batch_config_get(int* schedule, uint32_t* xcd_chunk, uint32_t* grid_cap_blocks, int* use_graph)
+{
+    if (!schedule || !xcd_chunk || !grid_cap_blocks || !use_graph) return HAMMING_EINVAL;
+    *schedule = g_schedule.load();
+    *xcd_chunk = g_xcd_chunk.load();
+    *grid_cap_blocks = g_grid_cap.load();
+    *use_graph = g_use_graph.load();
+    return HAMMING_OK;
+}
+
+int hamming_decode_batch(const uint64_t* cw_arena, uint64_t cw_words, const hamming_packet* descs,
+                         const uint32_t* n_packets_dev, uint32_t max_packets, uint64_t max_codewords,
+                         uint64_t* data_arena,
+                         uint64_t data_words, uint8_t* errpos_arena, uint64_t errpos_bytes,
+                         int32_t* status_out, void* workspace, uint64_t workspace_bytes, hipStream_t stream)
+{
+    if (max_packets > HAMMING_MAX_BATCH) return HAMMING_ERANGE;
+    if (max_packets == 0) return HAMMING_OK;
+    if (!cw_arena || !descs || !n_packets_dev || !data_arena || !workspace) return HAMMING_EINVAL;
+    if (misaligned(cw_arena, 8) || misaligned(data_arena, 8) || misaligned(descs, 8) ||
+        misaligned(n_packets_dev, 4) || misaligned(workspace, 8) || (status_out && misaligned(status_out, 4)))
+        return HAMMING_EALIGN;
+    if (workspace_bytes < hm::batch_workspace_bytes(max_packets)) return HAMMING_ENOMEM;
+
+    BatchArgs a;
+    memset(&a, 0, sizeof a);
+    a.cw_arena = cw_arena;
+    a.cw_words = cw_words;
+    a.descs = descs;
+    a.n_packets_dev = n_packets_dev;
+    a.max_packets = max_packets;
+    a.data_arena = data_arena;
+    a.data_words = data_words;
+    a.errpos_arena = errpos_arena;
+    a.errpos_bytes = errpos_arena ? errpos_bytes : 0;
+    a.status_out = status_out;
+    a.xcd_chunk = g_xcd_chunk.load();
+    a.coarse_cap = hm::batch_coarse_capacity(max_packets);
+    a.fine_cap = hm::batch_fine_capacity(max_packets);
+    a.ws = static_cast<hm::BatchWs*>(workspace);
+    a.tile_start = reinterpret_cast<uint64_t*>(static_cast<char*>(workspace) + sizeof(hm::BatchWs));
+    a.coarse = reinterpret_cast<uint32_t*>(a.tile_start + (uint64_t(max_packets) + 1));
+    a.fine = a.coarse + a.coarse_cap;
+
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HAMMING_EDEVICE;
+    const int schedule = g_schedule.load();
+    // One wave per tile of the largest batch these arguments allow; a smaller
+    // grid is still correct (waves loop), only slower.
+    const uint64_t tiles = (max_codewords ? max_codewords / hm::kMinTileCodewords : cw_words / hm::kMinTileWords) +
+                           uint64_t(max_packets);
+    uint64_t blocks = (tiles + hm::kWavesPerBlockHost - 1) / hm::kWavesPerBlockHost;
+    const uint64_t cap = g_grid_cap.load();
+    if (cap && blocks > cap) blocks = cap;
+    if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
+    if (blocks < 1) blocks = 1;
+    const uint32_t grid = uint32_t(blocks);
+
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (stream && hipStreamIsCapturing(stream, &cs) != hipSuccess) return HAMMING_EDEVICE;
+    if (stream && cs == hipStreamCaptureStatusNone && g_use_graph.load()) {
+        GraphKey key;
+        memset(&key, 0, sizeof key);
+        key.a = a;
+        key.schedule = schedule;
+        key.grid = grid;
+        key.stream = stream;
+        key.device = dev;
+        hipGraphExec_t exec = find_or_capture(key, stream);
+        if (exec) return hipGraphLaunch(exec, stream) == hipSuccess ? HAMMING_OK : HAMMING_EDEVICE;
+    }
+    return hm::launch_batch(a, schedule, grid, stream) == hipSuccess ? HAMMING_OK : HAMMING_EDEVICE;
+}
+
+}  // extern "C"

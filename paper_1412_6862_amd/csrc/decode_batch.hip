@@ -1,0 +1,243 @@
+// Batched decode: many packets of mixed size and r in one launch sequence.
+//
+// The arithmetic is the plain decode's (tile.h); only the work distribution
+// differs.  Four kernels, all replayable from a hipGraph with no host work:
+//  * batch_plan_kernel (one workgroup) validates every descriptor, writes its
+//    status and an exclusive prefix sum of its tile count (tiles are 64*U
+//    codewords aligned to the packet's start), and picks the group sizes of
+//    two tile-to-packet maps so that each fits its capacity;
+//  * batch_coarse_kernel fills the coarse map by binary search over the
+//    prefix sums; batch_fine_kernel fills the fine map (normally one entry
+//    per tile) by a short binary search between two coarse entries;
+//  * decode_batch_kernel gives one tile to each wave in global tile order, as
+//    the hardware dispatches the plain grid, so the tiles in flight form one
+//    advancing window of memory.  A wave reads its packet from the fine map
+//    (plus a 64-lane probe when a fine entry spans several tiles), then
+//    decodes the tile exactly as the plain kernel would.  A grid smaller than
+//    the batch loops.
+// Each packet's output is the same words a plain call would write.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "batch.h"
+#include "hamming.h"
+#include "hamming_device.h"
+#include "tile.h"
+
+namespace hm {
+
+// Per-r lane widths of a batch schedule.
+template <int U3, int U4, int U5, int U6, int U7>
+struct Schedule {
+    static constexpr int u[5] = {U3, U4, U5, U6, U7};
+    static constexpr int max2(int a, int b) { return a > b ? a : b; }
+    static constexpr int LDS_MAX =
+        max2(max2(max2(TileShape<3, U3>::LDS_DW, TileShape<4, U4>::LDS_DW),
+                  max2(TileShape<5, U5>::LDS_DW, TileShape<6, U6>::LDS_DW)),
+             TileShape<7, U7>::LDS_DW);
+    static_assert(valid_u(3, U3) && valid_u(4, U4) && valid_u(5, U5) && valid_u(6, U6) && valid_u(7, U7),
+                  "invalid lane width");
+};
+
+using Sched0 = Schedule<8, 8, 8, 8, 2>;
+using Sched1 = Schedule<8, 4, 4, 4, 2>;
+
+__device__ __forceinline__ uint64_t message_words(uint64_t n_cw, uint32_t r)
+{
+    const uint64_t k = (uint64_t(1) << r) - 1 - r;
+    return (n_cw * k + 63) / 64;
+}
+
+template <class S>
+__device__ __forceinline__ uint64_t packet_tiles(uint64_t n_cw, uint32_t r)
+{
+    const uint64_t cwt = 64u * uint64_t(S::u[r - 3]);
+    return (n_cw + cwt - 1) / cwt;
+}
+
+// Validate one descriptor; returns a status and the packet's tile count.
+template <class S>
+__device__ int32_t plan_packet(const hamming_packet& d, const BatchArgs& a, uint64_t* tiles)
+{
+    *tiles = 0;
+    if (d.r < 3 || d.r > 7 || d.flags != 0) return HAMMING_EINVAL;
+    if (d.n_cw > HAMMING_MAX_CODEWORDS) return HAMMING_ERANGE;
+    if (d.n_cw == 0) return HAMMING_OK;
+    const uint64_t wpc = d.r == 7 ? 2 : 1;
+    if (d.in_word_off > a.cw_words || d.n_cw * wpc > a.cw_words - d.in_word_off) return HAMMING_ERANGE;
+    const uint64_t mw = message_words(d.n_cw, d.r);
+    if (d.data_word_off > a.data_words || mw > a.data_words - d.data_word_off) return HAMMING_ERANGE;
+    if (d.errpos_off != HAMMING_NO_ERRPOS) {
+        if (!a.errpos_arena || d.errpos_off > a.errpos_bytes || d.n_cw > a.errpos_bytes - d.errpos_off)
+            return HAMMING_ERANGE;
+    }
+    *tiles = packet_tiles<S>(d.n_cw, d.r);
+    return HAMMING_OK;
+}
+
+template <class S>
+__global__ __launch_bounds__(1024) void batch_plan_kernel(BatchArgs a)
+{
+    __shared__ uint64_t wave_sums[16];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u;
+    const uint32_t wave = tid >> 6;
+    uint32_t n = *a.n_packets_dev;
+    if (n > a.max_packets) n = a.max_packets;
+    uint64_t carry = 0;
+    for (uint32_t base = 0; base < n; base += 1024) {
+        const uint32_t p = base + tid;
+        uint64_t t = 0;
+        if (p < n) {
+            const int32_t st = plan_packet<S>(a.descs[p], a, &t);
+            if (a.status_out) a.status_out[p] = st;
+        }
+        uint64_t x = t;   // inclusive scan within the wave
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint64_t y = __shfl_up(x, off);
+            if (lane >= uint32_t(off)) x += y;
+        }
+        if (lane == 63) wave_sums[wave] = x;
+        __syncthreads();
+        if (wave == 0) {
+            uint64_t v = lane < 16 ? wave_sums[lane] : 0;
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) {
+                const uint64_t y = __shfl_up(v, off);
+                if (lane >= uint32_t(off)) v += y;
+            }
+            if (lane < 16) wave_sums[lane] = v;
+        }
+        __syncthreads();
+        const uint64_t before = wave ? wave_sums[wave - 1] : 0;
+        if (p < n) a.tile_start[p] = carry + before + x - t;
+        carry += wave_sums[15];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        uint32_t gc = 0, gf = 0;
+        while ((carry >> gc) >= a.coarse_cap) ++gc;      // entries = ceil(total / 2^g) <= capacity
+        while ((carry >> gf) >= a.fine_cap) ++gf;
+        a.tile_start[n] = carry;
+        a.ws->total_tiles = carry;
+        a.ws->n_packets = n;
+        a.ws->coarse_log2 = gc;
+        a.ws->fine_log2 = gf;
+        a.ws->n_coarse = (carry + (uint64_t(1) << gc) - 1) >> gc;
+        a.ws->n_fine = (carry + (uint64_t(1) << gf) - 1) >> gf;
+    }
+}
+
+// Last p in [lo, hi) with ts[p] <= t, given ts[lo] <= t (per lane).
+__device__ __forceinline__ uint32_t search_packet(const uint64_t* ts, uint64_t t, uint32_t lo, uint32_t hi)
+{
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (ts[mid] <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void batch_coarse_kernel(BatchArgs a)
+{
+    const uint64_t j = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= a.ws->n_coarse) return;
+    a.coarse[j] = search_packet(a.tile_start, j << a.ws->coarse_log2, 0, uint32_t(a.ws->n_packets));
+}
+
+__global__ __launch_bounds__(256) void batch_fine_kernel(BatchArgs a)
+{
+    const uint64_t j = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= a.ws->n_fine) return;
+    const uint64_t t = j << a.ws->fine_log2;
+    const uint64_t jc = t >> a.ws->coarse_log2;
+    const uint32_t lo = a.coarse[jc];
+    // the packet holding tile t lies between the coarse entries around it
+    const uint32_t hi = (jc + 1 < a.ws->n_coarse) ? a.coarse[jc + 1] + 1 : uint32_t(a.ws->n_packets);
+    a.fine[j] = search_packet(a.tile_start, t, lo, hi);
+}
+
+// Last packet p in [0, n) with tile_start[p] <= t, given tile_start[lo] <= t
+// and t < tile_start[n] (t uniform across the wave): 64 lanes probe 64
+// consecutive entries per step.
+__device__ __forceinline__ uint32_t probe_packet(const uint64_t* ts, uint32_t n, uint64_t t, uint32_t lo)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    for (;;) {
+        const uint32_t q = lo + lane;
+        const bool le = (q < n) && (ts[q] <= t);
+        const uint64_t m = __ballot(le);                 // a prefix of the lanes: ts is non-decreasing
+        const uint32_t cnt = uint32_t(__popcll(m));
+        if (cnt < 64) return lo + cnt - 1;
+        lo += 63;
+    }
+}
+
+template <int R, int U>
+__device__ __forceinline__ void decode_packet_tile(const hamming_packet& d, uint64_t tl, const BatchArgs& a,
+                                                   uint32_t* lds)
+{
+    const uint64_t* cw = a.cw_arena + d.in_word_off;
+    uint64_t* data = a.data_arena + d.data_word_off;
+    uint8_t* ep = (d.errpos_off == HAMMING_NO_ERRPOS) ? nullptr : a.errpos_arena + d.errpos_off;
+    uint32_t flags = 0;
+    if ((reinterpret_cast<uintptr_t>(cw) & 15u) == 0) flags |= kFlagIn16;
+    if (ep && (reinterpret_cast<uintptr_t>(ep) % U) == 0) flags |= kFlagEpVec;
+    if ((reinterpret_cast<uintptr_t>(data) & 15u) == 0) flags |= kFlagOut16;
+    decode_tile<R, U>(cw, d.n_cw, tl, data, message_words(d.n_cw, R), ep, lds, flags);
+}
+
+template <class S>
+__global__ __launch_bounds__(kBlockThreads) void decode_batch_kernel(BatchArgs a)
+{
+    __shared__ u32x4 lds_raw[kWavesPerBlock][S::LDS_MAX / 4];
+    uint32_t* lds = reinterpret_cast<uint32_t*>(&lds_raw[threadIdx.x >> 6][0]);
+    const uint64_t total = a.ws->total_tiles;
+    const uint64_t waves = uint64_t(gridDim.x) * kWavesPerBlock;
+    uint64_t t = uint64_t(xcd_block(blockIdx.x, gridDim.x, a.xcd_chunk)) * kWavesPerBlock + (threadIdx.x >> 6);
+    if (t >= total) return;
+    const uint32_t n = uint32_t(a.ws->n_packets);
+    const uint32_t gf = a.ws->fine_log2;
+    const uint64_t* ts = a.tile_start;
+    for (; t < total; t += waves) {
+        uint32_t p = a.fine[t >> gf];
+        if (gf) p = probe_packet(ts, n, t, p);
+        const hamming_packet d = a.descs[p];
+        const uint64_t tl = t - ts[p];
+        switch (d.r) {
+        case 3: decode_packet_tile<3, S::u[0]>(d, tl, a, lds); break;
+        case 4: decode_packet_tile<4, S::u[1]>(d, tl, a, lds); break;
+        case 5: decode_packet_tile<5, S::u[2]>(d, tl, a, lds); break;
+        case 6: decode_packet_tile<6, S::u[3]>(d, tl, a, lds); break;
+        default: decode_packet_tile<7, S::u[4]>(d, tl, a, lds); break;
+        }
+    }
+}
+
+template <class S>
+static hipError_t launch_batch_s(const BatchArgs& a, uint32_t grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL((batch_plan_kernel<S>), dim3(1), dim3(1024), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_coarse_kernel, dim3((a.coarse_cap + 255) / 256), dim3(256), 0, stream, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_fine_kernel, dim3((a.fine_cap + 255) / 256), dim3(256), 0, stream, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((decode_batch_kernel<S>), dim3(grid), dim3(kBlockThreads), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchArgs& a, int schedule, uint32_t grid, hipStream_t stream)
+{
+    switch (schedule) {
+    case 0: return launch_batch_s<Sched0>(a, grid, stream);
+    case 1: return launch_batch_s<Sched1>(a, grid, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace hm

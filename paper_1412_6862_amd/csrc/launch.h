@@ -9,6 +9,7 @@ namespace hm {
 // Kernel flag bits, decided on the host from pointer alignment.
 constexpr uint32_t kFlagIn16 = 1u;    // codeword input is 16-byte aligned
 constexpr uint32_t kFlagEpVec = 2u;   // errpos output is aligned to U bytes
+constexpr uint32_t kFlagOut16 = 4u;   // message output is 16-byte aligned
 
 struct DecodeLaunch {
     int r;
@@ -19,6 +20,7 @@ struct DecodeLaunch {
     uint64_t data_words;
     uint8_t* errpos;
     uint64_t max_blocks;    // 0 = one wave per tile
+    uint32_t xcd_chunk;     // blocks per XCD slice (1 = hardware order)
 };
 
 // Smallest lane width that gives every lane chunk at least one dword.

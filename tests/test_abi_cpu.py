@@ -77,8 +77,10 @@ def test_encode_validation_codes():
 def test_plain_config_roundtrip_and_validation():
     old = {r: hm.hamming_plain_config_get(r) for r in range(3, 8)}
     try:
-        hm.hamming_plain_config_set(6, 8, 1024)
-        assert hm.hamming_plain_config_get(6) == (8, 1024)
+        hm.hamming_plain_config_set(6, 8, 1024, 16)
+        assert hm.hamming_plain_config_get(6) == (8, 1024, 16)
+        with pytest.raises(hm.HammingError):
+            hm.hamming_plain_config_set(6, 8, 0, 0)
         with pytest.raises(hm.HammingError):
             hm.hamming_plain_config_set(3, 4, 0)      # 4 * 4 bits < one dword
         with pytest.raises(hm.HammingError):
@@ -86,8 +88,8 @@ def test_plain_config_roundtrip_and_validation():
         with pytest.raises(hm.HammingError):
             hm.hamming_plain_config_set(9, 4, 0)
     finally:
-        for r, (u, mb) in old.items():
-            hm.hamming_plain_config_set(r, u, mb)
+        for r, cfg in old.items():
+            hm.hamming_plain_config_set(r, *cfg)
 
 
 def test_strerror_texts():
@@ -95,3 +97,85 @@ def test_strerror_texts():
         assert isinstance(hm.strerror(code), str) and hm.strerror(code)
     err = hm.HammingError(hm.HAMMING_EALIGN, "x")
     assert "aligned" in str(err)
+
+
+def test_batch_layout_host_helper():
+    import numpy as np
+
+    d = np.zeros(5, dtype=hm.packet_dtype())
+    d["n_cw"] = [100, 0, 7, 64, 1]
+    d["r"] = [3, 7, 5, 6, 7]
+    dw, eb = hm.hamming_batch_layout(d)
+    words = [(n * k + 63) // 64 for n, k in zip(d["n_cw"], [4, 120, 26, 57, 120])]
+    off = 0
+    eoff = 0
+    for i in range(5):
+        assert d[i]["data_word_off"] == off and d[i]["data_word_off"] % 2 == 0
+        assert d[i]["errpos_off"] == eoff and eoff % 16 == 0
+        off += words[i] + (words[i] & 1)
+        eoff += (int(d["n_cw"][i]) + 15) // 16 * 16
+    assert (dw, eb) == (off, eoff)
+    bad = d.copy()
+    bad[2]["r"] = 2
+    before = bad.copy()
+    with pytest.raises(hm.HammingError):
+        hm.hamming_batch_layout(bad)
+    assert np.array_equal(bad, before)
+
+
+def test_batch_workspace_and_validation_codes():
+    lib = hm.library()
+    assert hm.hamming_batch_workspace_bytes(0) >= 64
+    assert hm.hamming_batch_workspace_bytes(1000) >= 64 + 8 * 1001 + 4 * 3024 + 4 * (1 << 22)
+    assert hm.hamming_batch_workspace_bytes(hm.HAMMING_MAX_BATCH + 1) == 0
+    A = 1 << 20
+    ws = hm.hamming_batch_workspace_bytes(10)
+    call = lambda **kw: lib.hamming_decode_batch(
+        kw.get("cw", A), 100, kw.get("descs", A), kw.get("n", A), kw.get("maxp", 10), 0, kw.get("data", A), 100,
+        A, 100, kw.get("status", A), kw.get("ws", A), kw.get("wsb", ws), 0)
+    assert call(maxp=0) == hm.HAMMING_OK
+    assert call(maxp=hm.HAMMING_MAX_BATCH + 1) == hm.HAMMING_ERANGE
+    assert call(cw=0) == hm.HAMMING_EINVAL
+    assert call(descs=0) == hm.HAMMING_EINVAL
+    assert call(n=0) == hm.HAMMING_EINVAL
+    assert call(ws=0) == hm.HAMMING_EINVAL
+    assert call(cw=A + 4) == hm.HAMMING_EALIGN
+    assert call(descs=A + 4) == hm.HAMMING_EALIGN
+    assert call(status=A + 2) == hm.HAMMING_EALIGN
+    assert call(wsb=ws - 8) == hm.HAMMING_ENOMEM
+
+
+def test_batch_config_roundtrip():
+    old = hm.hamming_batch_config_get()
+    try:
+        hm.hamming_batch_config_set(1, 4, 4096, 0)
+        assert hm.hamming_batch_config_get() == (1, 4, 4096, 0)
+        for args in ((2, 2, 8, 1), (-1, 2, 8, 1), (0, 2, 8, 2), (0, 0, 0, 1), (0, (1 << 20) + 1, 0, 1)):
+            with pytest.raises(hm.HammingError):
+                hm.hamming_batch_config_set(*args)
+    finally:
+        hm.hamming_batch_config_set(*old)
+
+
+def test_server_create_validation_codes():
+    lib = hm.library()
+    import ctypes
+
+    A = 1 << 20
+    h = ctypes.c_void_p()
+    good = hm.hamming_server_config(2, 16, 1 << 20, 64, 1)
+    assert lib.hamming_server_create(None, A, 100, A, 1 << 20, ctypes.byref(h)) == hm.HAMMING_EINVAL
+    assert lib.hamming_server_create(ctypes.byref(good), 0, 100, A, 1 << 20, ctypes.byref(h)) == hm.HAMMING_EINVAL
+    assert lib.hamming_server_create(ctypes.byref(good), A, 0, A, 1 << 20, ctypes.byref(h)) == hm.HAMMING_EINVAL
+    assert lib.hamming_server_create(ctypes.byref(good), A, 100, A, 100, ctypes.byref(h)) == hm.HAMMING_EINVAL
+    assert lib.hamming_server_create(ctypes.byref(good), A + 4, 100, A, 1 << 20, ctypes.byref(h)) == hm.HAMMING_EALIGN
+    assert lib.hamming_server_create(ctypes.byref(good), A, 100, A + 8, 1 << 20, ctypes.byref(h)) == hm.HAMMING_EALIGN
+    for bad in (hm.hamming_server_config(0, 16, 1, 64, 1), hm.hamming_server_config(17, 16, 1, 64, 1),
+                hm.hamming_server_config(2, 0, 1, 64, 1), hm.hamming_server_config(2, 16, 0, 64, 1),
+                hm.hamming_server_config(2, 16, 1, 0, 1), hm.hamming_server_config(2, 16, 1, 64, 2)):
+        assert lib.hamming_server_create(ctypes.byref(bad), A, 100, A, 1 << 20, ctypes.byref(h)) == hm.HAMMING_EINVAL
+    assert lib.hamming_server_destroy(None) == hm.HAMMING_EINVAL
+    assert lib.hamming_server_progress(None) == hm.HAMMING_EINVAL
+    n = ctypes.c_uint32()
+    assert lib.hamming_server_poll(None, None, 0, ctypes.byref(n)) == hm.HAMMING_EINVAL
+    assert hm.hamming_server_now_ns() > 0

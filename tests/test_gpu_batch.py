@@ -1,0 +1,238 @@
+"""GPU parity of the batched decode: every packet of a batched launch is
+byte-identical to the oracle (and so to a plain call on that packet alone),
+output bytes between packets are untouched, invalid descriptors are flagged
+and skipped, and graph replays stay correct.  Tolerance: 0 bits."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1412_6862_amd as hm
+import synth
+from _inputs import received_words
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [0, 1, 2, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1000, 4097, 9999]
+
+
+def _build_batch(seed, n_packets, sizes=None, rs=None, gap_words=True):
+    """Host arena of received words and a descriptor array (offsets not laid out)."""
+    rng = np.random.default_rng(seed)
+    if sizes is None:
+        sizes = [int(rng.choice(SIZES)) for _ in range(n_packets)]
+    if rs is None:
+        rs = [int(rng.integers(3, 8)) for _ in range(n_packets)]
+    descs = np.zeros(n_packets, dtype=hm.packet_dtype())
+    chunks, off = [], 0
+    ys = []
+    for i, (n_cw, r) in enumerate(zip(sizes, rs)):
+        gap = int(rng.integers(0, 3)) if gap_words else 0     # odd gaps give 8-byte-aligned packets
+        if gap:
+            chunks.append(np.full(gap, 0xDEADBEEF, dtype=np.uint64))
+            off += gap
+        y = received_words(synth.workload_seed("batch", r, seed * 100003 + i), n_cw, r,
+                           p_single=0.3, p_double=0.1) if n_cw else np.zeros(0, dtype=np.uint64)
+        descs[i]["in_word_off"] = off
+        descs[i]["n_cw"] = n_cw
+        descs[i]["r"] = r
+        chunks.append(y)
+        ys.append(y)
+        off += y.size
+    arena = np.concatenate(chunks + [np.zeros(2, dtype=np.uint64)])
+    return arena, descs, ys
+
+
+def _expect(ys, descs):
+    return [oracle.decode(y, int(d["r"])) for y, d in zip(ys, descs)]
+
+
+def _to_dev(a, dev):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to(dev)
+
+
+def _check_outputs(bd, descs, expect, data_fill=None, ep_fill=None, skip=()):
+    data = bd.data.cpu().numpy().view(np.uint8)
+    ep = bd.errpos.cpu().numpy()
+    covered_d = np.zeros(data.size, dtype=bool)
+    covered_e = np.zeros(ep.size, dtype=bool)
+    for i, (d, (dref, eref)) in enumerate(zip(descs, expect)):
+        if i in skip:
+            continue
+        o = int(d["data_word_off"]) * 8
+        assert np.array_equal(data[o:o + dref.size], dref), "packet %d data" % i
+        covered_d[o:o + dref.size] = True
+        if int(d["errpos_off"]) != hm.HAMMING_NO_ERRPOS:
+            e = int(d["errpos_off"])
+            assert np.array_equal(ep[e:e + eref.size], eref), "packet %d errpos" % i
+            covered_e[e:e + eref.size] = True
+    if data_fill is not None:
+        assert (data[~covered_d] == data_fill).all()
+    if ep_fill is not None:
+        assert (ep[~covered_e] == ep_fill).all()
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_batch_matches_oracle_and_leaves_gaps(gpu_device, seed):
+    import torch
+
+    arena, descs, ys = _build_batch(seed, 60)
+    expect = _expect(ys, descs)
+    cw = _to_dev(arena, gpu_device)
+    bd = hm.BatchDecoder(cw, 64)
+    bd.set_packets(descs)
+    bd.data.fill_(0x5A5A5A5A5A5A5A5A)
+    bd.errpos.fill_(0xA5)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        bd.decode(stream=s)
+    torch.cuda.synchronize()
+    assert not bd.status[:descs.size].cpu().numpy().any()
+    _check_outputs(bd, descs, expect, data_fill=0x5A, ep_fill=0xA5)
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("xcd_chunk", [1, 3, 64])
+@pytest.mark.parametrize("grid_cap", [0, 1, 5])
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_batch_every_schedule_grid_and_launch_mode(gpu_device, schedule, xcd_chunk, grid_cap, use_graph):
+    import torch
+
+    old = hm.hamming_batch_config_get()
+    arena, descs, ys = _build_batch(7 + grid_cap + 10 * xcd_chunk, 40)
+    expect = _expect(ys, descs)
+    cw = _to_dev(arena, gpu_device)
+    try:
+        hm.hamming_batch_config_set(schedule, xcd_chunk, grid_cap, use_graph)
+        bd = hm.BatchDecoder(cw, 40)
+        bd.set_packets(descs)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            bd.decode(stream=s)
+        torch.cuda.synchronize()
+        _check_outputs(bd, descs, expect)
+    finally:
+        hm.hamming_batch_config_set(*old)
+
+
+def test_batch_on_default_stream(gpu_device):
+    import torch
+
+    arena, descs, ys = _build_batch(11, 25)
+    expect = _expect(ys, descs)
+    bd = hm.BatchDecoder(_to_dev(arena, gpu_device), 25)
+    bd.set_packets(descs)
+    bd.decode(stream=0)
+    torch.cuda.synchronize()
+    _check_outputs(bd, descs, expect)
+
+
+def test_batch_packet_equals_plain_call(gpu_device):
+    import torch
+
+    arena, descs, ys = _build_batch(21, 12, sizes=[5000] * 12, rs=[3, 4, 5, 6, 7, 7, 6, 5, 4, 3, 6, 7])
+    cw = _to_dev(arena, gpu_device)
+    bd = hm.BatchDecoder(cw, 12)
+    bd.set_packets(descs)
+    bd.decode()
+    torch.cuda.synchronize()
+    data = bd.data.cpu().numpy().view(np.uint8)
+    ep = bd.errpos.cpu().numpy()
+    for i, d in enumerate(descs):
+        r, n_cw = int(d["r"]), int(d["n_cw"])
+        wpc = hm.words_per_codeword(r)
+        o = int(d["in_word_off"])
+        pd, pe = hm.decode(cw[o:o + n_cw * wpc], r)
+        torch.cuda.synchronize()
+        pd = pd.cpu().numpy()
+        assert np.array_equal(data[int(d["data_word_off"]) * 8:][:pd.size], pd)
+        assert np.array_equal(ep[int(d["errpos_off"]):][:n_cw], pe.cpu().numpy())
+
+
+def test_batch_invalid_descriptors_are_flagged_and_skipped(gpu_device):
+    import torch
+
+    arena, descs, ys = _build_batch(31, 10, sizes=[300] * 10, rs=[4, 5, 6, 7, 3, 4, 5, 6, 7, 3])
+    expect = _expect(ys, descs)
+    hm.hamming_batch_layout(descs)
+    dw = int(max(d["data_word_off"] for d in descs)) + 64
+    eb = int(max(d["errpos_off"] for d in descs)) + 512
+    bad = descs.copy()
+    bad[1]["r"] = 9                                   # bad r
+    bad[3]["flags"] = 1                               # reserved flags
+    bad[5]["in_word_off"] = arena.size                # codewords past the arena
+    bad[7]["data_word_off"] = dw                      # message range past the arena
+    bad[9]["errpos_off"] = eb - 100                   # errpos range past the arena
+    bad[8]["errpos_off"] = hm.HAMMING_NO_ERRPOS       # valid: no errpos wanted
+    cw = _to_dev(arena, gpu_device)
+    bd = hm.BatchDecoder(cw, 10)
+    bd.set_packets(bad, layout=False, data_words=dw, errpos_bytes=eb)
+    bd.data.fill_(0x1111111111111111)
+    bd.errpos.fill_(0x22)
+    bd.decode()
+    torch.cuda.synchronize()
+    st = bd.status.cpu().numpy()[:10]
+    assert list(st) == [0, hm.HAMMING_EINVAL, 0, hm.HAMMING_EINVAL, 0, hm.HAMMING_ERANGE, 0,
+                        hm.HAMMING_ERANGE, 0, hm.HAMMING_ERANGE]
+    _check_outputs(bd, bad, expect, skip=(1, 3, 5, 7, 9))
+    # skipped packets wrote nothing into their laid-out ranges
+    data = bd.data.cpu().numpy().view(np.uint8)
+    for i in (1, 3, 5):
+        o = int(descs[i]["data_word_off"]) * 8
+        assert (data[o:o + expect[i][0].size] == 0x11).all()
+
+
+def test_batch_device_count_below_max_and_graph_replays(gpu_device):
+    """One graph serves several batch sizes: the packet count lives on the
+    device.  Replays are checked one by one, with eager work in between."""
+    import torch
+
+    arena, descs, ys = _build_batch(41, 30)
+    expect = _expect(ys, descs)
+    cw = _to_dev(arena, gpu_device)
+    bd = hm.BatchDecoder(cw, 30)
+    bd.set_packets(descs)
+    s = torch.cuda.Stream()
+    for n in (30, 7, 0, 19, 30, 1):
+        bd.data.fill_(0x3333333333333333)
+        bd.errpos.fill_(0x44)
+        bd.n_dev.fill_(n)
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            bd.decode(stream=s)
+        torch.cuda.synchronize()
+        _check_outputs(bd, descs[:n], expect[:n], data_fill=0x33, ep_fill=0x44)
+
+
+def test_batch_empty_and_all_empty(gpu_device):
+    import torch
+
+    arena = np.zeros(4, dtype=np.uint64)
+    cw = _to_dev(arena, gpu_device)
+    bd = hm.BatchDecoder(cw, 4)
+    descs = np.zeros(4, dtype=hm.packet_dtype())
+    descs["r"] = [3, 4, 5, 7]
+    bd.set_packets(descs)
+    bd.decode()
+    torch.cuda.synchronize()
+    assert not bd.status.cpu().numpy().any()
+
+
+def test_batch_small_grid_hint_and_coarse_map(gpu_device):
+    """A max_codewords hint far below the batch (grid smaller than the tile
+    count: waves loop) and a map whose groups span many tiles (more tiles than
+    map entries) still decode every packet exactly."""
+    import torch
+
+    arena, descs, ys = _build_batch(51, 3, sizes=[300000, 77, 250000], rs=[4, 7, 3])
+    expect = _expect(ys, descs)
+    bd = hm.BatchDecoder(_to_dev(arena, gpu_device), 3)
+    bd.set_packets(descs)
+    for hint in (1, 1000, 0):
+        bd.data.fill_(0x6666666666666666)
+        bd.decode(max_codewords=hint)
+        torch.cuda.synchronize()
+        _check_outputs(bd, descs, expect)

@@ -58,8 +58,8 @@ def test_plain_every_lane_shape_and_grid_cap(gpu_device, r):
         for u in (2, 4, 8, 16):
             if u * hm.hamming_message_bits(r) < 32:
                 continue
-            for cap in (0, 1, 3, 64):
-                hm.hamming_plain_config_set(r, u, cap)
+            for cap, chunk in ((0, 1), (1, 1), (3, 2), (64, 4), (0, 3), (0, 64)):
+                hm.hamming_plain_config_set(r, u, cap, chunk)
                 _check(y, r, gpu_device)
     finally:
         hm.hamming_plain_config_set(r, *old)
@@ -77,11 +77,16 @@ def test_plain_unaligned_input_and_errpos(gpu_device, r):
     big[1:] = to_device(y, gpu_device)
     cw = big[1:]                                   # 8-byte but not 16-byte aligned
     assert cw.data_ptr() % 16 == 8
-    data = torch.empty(hm.hamming_data_bytes(n_cw, r), dtype=torch.uint8, device=gpu_device)
+    nbytes = hm.hamming_data_bytes(n_cw, r)
+    dbuf = torch.zeros(nbytes + 16, dtype=torch.uint8, device=gpu_device)
+    data = dbuf[8:8 + nbytes]                      # 8-byte but not 16-byte aligned
+    assert data.data_ptr() % 16 == 8
     epbuf = torch.zeros(n_cw + 3, dtype=torch.uint8, device=gpu_device)
     hm.hamming_decode(cw, n_cw, r, data, epbuf[1:])
     torch.cuda.synchronize()
     assert np.array_equal(to_host_u8(data), d_ref)
+    db = to_host_u8(dbuf)
+    assert not db[:8].any() and not db[8 + nbytes:].any()
     ep = to_host_u8(epbuf)
     assert np.array_equal(ep[1:n_cw + 1], e_ref)
     assert ep[0] == 0 and not ep[n_cw + 1:].any()

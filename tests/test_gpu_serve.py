@@ -1,0 +1,183 @@
+"""GPU tests of the serving core: every request's result is the same decoded
+alone (plain call), in the mix (continuous batching) and by the oracle;
+admission waits for output memory; batches overlap; the open-loop trace
+runner completes.  Tolerance: 0 bits."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1412_6862_amd as hm
+import synth
+from _inputs import received_words
+
+pytestmark = pytest.mark.gpu
+
+
+def _pool(seed, sizes, rs):
+    chunks, offs, ys = [], [], []
+    off = 0
+    for i, (n_cw, r) in enumerate(zip(sizes, rs)):
+        y = received_words(synth.workload_seed("serve", r, seed * 7919 + i), n_cw, r, p_single=0.1, p_double=0.02)
+        offs.append(off)
+        chunks.append(y)
+        ys.append(y)
+        off += y.size
+    return np.concatenate(chunks + [np.zeros(2, dtype=np.uint64)]), offs, ys
+
+
+def _to_dev(a, dev):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to(dev)
+
+
+def _drain(srv, want, limit=200000):
+    got = {}
+    for _ in range(limit):
+        srv.progress()
+        for c in srv.poll():
+            got[c.request_id] = c
+        if len(got) >= want:
+            return got
+    raise AssertionError("server did not finish: %d of %d" % (len(got), want))
+
+
+def _check_request(srv, c, y, r, cw_dev, off):
+    import torch
+
+    assert c.status == 0
+    n_cw = y.size // hm.words_per_codeword(r)
+    d, e = srv.result(c, r, n_cw)
+    torch.cuda.synchronize()
+    d_mix, e_mix = d.cpu().numpy(), e.cpu().numpy()
+    d_ref, e_ref = oracle.decode(y, r)
+    assert np.array_equal(d_mix, d_ref) and np.array_equal(e_mix, e_ref)
+    wpc = hm.words_per_codeword(r)
+    d_alone, e_alone = hm.decode(cw_dev[off:off + n_cw * wpc], r)
+    torch.cuda.synchronize()
+    assert np.array_equal(d_mix, d_alone.cpu().numpy()) and np.array_equal(e_mix, e_alone.cpu().numpy())
+
+
+def test_serve_results_same_alone_in_mix_and_oracle(gpu_device):
+    rng = np.random.default_rng(5)
+    n = 48
+    sizes = [int(rng.choice([1, 63, 64, 65, 300, 4097, 20000, 70000])) for _ in range(n)]
+    rs = [int(rng.integers(4, 8)) for _ in range(n)]
+    pool, offs, ys = _pool(1, sizes, rs)
+    cw = _to_dev(pool, gpu_device)
+    srv = hm.Server(cw, slots=3, max_batch_packets=8, max_batch_codewords=100000, output_pool_bytes=64 << 20)
+    try:
+        ids = {}
+        for i in range(n):                     # arrivals interleaved with progress: continuous batching
+            ids[srv.submit(offs[i], sizes[i], rs[i])] = i
+            if i % 5 == 4:
+                srv.progress()
+        got = _drain(srv, n)
+        assert srv.stats()["batches"] >= n // 8
+        for rid, c in got.items():
+            i = ids[rid]
+            _check_request(srv, c, ys[i], rs[i], cw, offs[i])
+            srv.release(rid)
+        assert srv.stats()["output_bytes_used"] == 0
+    finally:
+        srv.close()
+
+
+def test_serve_batches_overlap_in_flight(gpu_device):
+    sizes = [1 << 20] * 6
+    rs = [5, 6, 7, 4, 5, 6]
+    pool, offs, ys = _pool(2, sizes, rs)
+    cw = _to_dev(pool, gpu_device)
+    srv = hm.Server(cw, slots=2, max_batch_packets=4, max_batch_codewords=1 << 20, output_pool_bytes=256 << 20)
+    try:
+        ids = {srv.submit(offs[i], sizes[i], rs[i]): i for i in range(6)}
+        srv.progress()
+        st = srv.stats()
+        # two one-request batches are on the GPU at once; four requests wait
+        assert st["inflight"] == 2 and st["queued"] == 4 and st["batches"] == 2
+        got = _drain(srv, 6)
+        for rid, c in got.items():
+            _check_request(srv, c, ys[ids[rid]], rs[ids[rid]], cw, offs[ids[rid]])
+            srv.release(rid)
+    finally:
+        srv.close()
+
+
+def test_serve_admission_waits_for_output_memory(gpu_device):
+    sizes = [50000] * 10
+    rs = [7] * 10
+    pool, offs, ys = _pool(3, sizes, rs)
+    cw = _to_dev(pool, gpu_device)
+    one = ((50000 * 120 + 63) // 64) * 8 + 50000
+    srv = hm.Server(cw, slots=4, max_batch_packets=16, max_batch_codewords=1 << 30,
+                    output_pool_bytes=2 * one + 4096, auto_release=False)
+    try:
+        ids = {srv.submit(offs[i], sizes[i], rs[i]): i for i in range(10)}
+        srv.progress()
+        st = srv.stats()
+        assert st["inflight"] <= 2 and st["queued"] >= 8       # only two requests' outputs fit
+        done = 0
+        while done < 10:
+            srv.progress()
+            for c in srv.poll():
+                _check_request(srv, c, ys[ids[c.request_id]], 7, cw, offs[ids[c.request_id]])
+                srv.release(c.request_id)                      # frees room for the next ones
+                done += 1
+    finally:
+        srv.close()
+
+
+def test_serve_submit_validation(gpu_device):
+    pool = np.zeros(1000, dtype=np.uint64)
+    cw = _to_dev(pool, gpu_device)
+    srv = hm.Server(cw, slots=1, max_batch_packets=4, output_pool_bytes=1 << 20, max_queue=8)
+    try:
+        for args, code in (((0, 10, 8), hm.HAMMING_EINVAL), ((0, 10, 2), hm.HAMMING_EINVAL),
+                           ((990, 20, 4), hm.HAMMING_ERANGE), ((0, 501, 7), hm.HAMMING_ERANGE),
+                           ((2000, 0, 4), hm.HAMMING_ERANGE)):
+            with pytest.raises(hm.HammingError) as e:
+                srv.submit(*args)
+            assert e.value.status == code
+        srv.submit(0, 500, 7)                                   # exactly the whole pool
+        srv.submit(1000, 0, 4)                                  # empty request at the end
+        got = _drain(srv, 2)
+        assert all(c.status == 0 for c in got.values())
+    finally:
+        srv.close()
+
+
+def test_serve_queue_limit(gpu_device):
+    pool = np.zeros(1000, dtype=np.uint64)
+    cw = _to_dev(pool, gpu_device)
+    srv = hm.Server(cw, slots=1, max_batch_packets=4, output_pool_bytes=1 << 20, max_queue=2)
+    try:
+        srv.submit(0, 10, 4)
+        srv.submit(10, 10, 4)
+        with pytest.raises(hm.HammingError) as e:
+            srv.submit(20, 10, 4)
+        assert e.value.status == hm.HAMMING_ENOMEM
+        _drain(srv, 2)
+    finally:
+        srv.close()
+
+
+def test_serve_open_loop_trace(gpu_device):
+    rng = np.random.default_rng(9)
+    n = 400
+    pool_words = 1 << 24
+    cw = _to_dev(synth.draws(77, 0, pool_words), gpu_device)
+    rs = rng.integers(4, 8, size=n).astype(np.uint32)
+    sizes = np.floor(256 * np.exp2(10 * rng.random(n))).astype(np.uint64)
+    wpc = np.where(rs == 7, 2, 1).astype(np.uint64)
+    offs = (rng.random(n) * (pool_words - sizes * wpc - 1)).astype(np.uint64)
+    gaps = rng.exponential(20e3, size=n)                     # mean 20 us between arrivals
+    arrivals = np.cumsum(gaps).astype(np.uint64)
+    srv = hm.Server(cw, slots=4, max_batch_packets=256, max_batch_codewords=1 << 24,
+                    output_pool_bytes=1 << 30, auto_release=True)
+    try:
+        lat, elapsed = srv.run_trace(arrivals, offs, sizes, rs, timeout_s=60)
+        assert (lat > 0).all() and lat.max() < 5e9
+        assert elapsed >= int(arrivals[-1])
+        assert srv.stats()["output_bytes_used"] == 0
+    finally:
+        srv.close()
