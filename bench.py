@@ -85,6 +85,188 @@ def make_packet(r: int, n_cw: int, p: float, dev):
     return cw
 
 
+def build_batch(dev, n_packets: int, seed: int):
+    """The batched workload: packet sizes log-uniform in [64, 2^20] codewords,
+    r uniform in 3..7, per-packet single-error rate uniform in [0, 0.5].
+    Messages and flips come from the seeded generator on the device; codewords
+    from the library's encoder.  Returns (arena, descs, per-r plain packets)."""
+    import numpy as np
+    import torch
+
+    import paper_1412_6862_amd as hm
+    import synth
+
+    n_cw, r, p = synth.batch_packets(seed, n_packets)
+    wpc = np.where(r == 7, 2, 1)
+    words = n_cw * wpc
+    in_off = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    descs = np.zeros(n_packets, dtype=hm.packet_dtype())
+    descs["in_word_off"] = in_off
+    descs["n_cw"] = n_cw
+    descs["r"] = r
+    hm.hamming_batch_layout(descs)
+    arena = torch.empty(int(words.sum()), dtype=torch.int64, device=dev)
+    per_r = {}
+    for rr in range(3, 8):
+        idx = np.flatnonzero(r == rr)
+        total = int(n_cw[idx].sum())
+        if total == 0:
+            continue
+        sr = synth.subseed(seed, "r", rr)
+        msg = synth.message_stream_torch(sr, total, rr, dev)
+        cw = hm.encode(msg, total, rr)
+        del msg
+        rates = torch.repeat_interleave(torch.from_numpy(p[idx]).to(dev),
+                                        torch.from_numpy(n_cw[idx]).to(dev))
+        cw ^= synth.flip_masks_torch(sr, total, rr, rates, dev)
+        del rates
+        w = 2 if rr == 7 else 1
+        pos = 0
+        for i in idx:
+            nw = int(n_cw[i]) * w
+            o = int(in_off[i])
+            arena[o:o + nw].copy_(cw[pos:pos + nw])
+            pos += nw
+        per_r[rr] = (cw, total)
+        torch.cuda.synchronize()
+    return arena, descs, per_r, n_cw, r
+
+
+def time_events(fn, stream, warmup: int, reps: int):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return sorted(a.elapsed_time(b) for a, b in evs)
+
+
+def batched_leg(dev, n_packets: int, reps: int):
+    """Batched decode of the whole workload in one hamming_decode_batch call,
+    beside the plain decode of the same codewords (one call per r)."""
+    import torch
+
+    import paper_1412_6862_amd as hm
+    import synth
+
+    seed = synth.workload_seed("bench-batch", 0)
+    arena, descs, per_r, n_cw, r = build_batch(dev, n_packets, seed)
+    bd = hm.BatchDecoder(arena, n_packets)
+    bd.set_packets(descs)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        tb = time_events(lambda: bd.decode(stream=stream), stream, 2, reps)
+    st = bd.status[:n_packets].cpu()
+    if bool((st != 0).any()):
+        raise RuntimeError("batched bench: a descriptor was rejected")
+    plain_ms = 0.0
+    data = torch.empty(max(hm.hamming_data_bytes(t, rr) for rr, (_, t) in per_r.items()), dtype=torch.uint8,
+                       device=dev)
+    ep = torch.empty(max(t for _, t in per_r.values()), dtype=torch.uint8, device=dev)
+    with torch.cuda.stream(stream):
+        for rr, (cw, total) in per_r.items():
+            tp = time_events(lambda: hm.hamming_decode(cw, total, rr, data, ep, stream), stream, 2, reps)
+            plain_ms += tp[len(tp) // 2]
+    k = (1 << r) - 1 - r
+    bits = float((n_cw * k).sum())
+    algo = float(sum(n_cw[r == rr].sum() * algorithmic_bytes_per_codeword(rr) for rr in range(3, 8)))
+    med = tb[len(tb) // 2]
+    del arena, per_r, bd, data, ep
+    torch.cuda.empty_cache()
+    return {
+        "workload": "%d packets, sizes log-uniform in [64, 2^20] codewords, r uniform in 3..7, per-packet "
+                    "single-error rate uniform in [0, 0.5]; one hamming_decode_batch call" % n_packets,
+        "packets": n_packets, "codewords": int(n_cw.sum()),
+        "algorithmic_bytes": int(algo),
+        "ms_p50": round(med, 3), "ms_min": round(tb[0], 3),
+        "payload_Gbps": round(bits / med / 1e6, 1),
+        "frac_hbm": round(algo / med / 1e6 / HBM_PEAK_GBPS, 4),
+        "plain_same_mix_ms": round(plain_ms, 3),
+        "batched_over_plain": round(plain_ms / med, 4),
+        "schedule": list(hm.hamming_batch_config_get()),
+    }
+
+
+def serving_leg(dev, plain_gBps_per_r: dict, loads, n_requests: int, warm: int):
+    """Open-loop serving: Poisson arrivals from 256 simulated SDR streams
+    (stream s decodes code r = 4 + s % 4), request sizes log-uniform in
+    [256, 2^18] codewords, 10% single-bit errors, offered load swept as a
+    fraction of the plain decoder's throughput on the same r-mix."""
+    import numpy as np
+    import torch
+
+    import paper_1412_6862_amd as hm
+    import synth
+
+    rs = (4, 5, 6, 7)
+    pool_cw = {4: 1 << 25, 5: 1 << 25, 6: 1 << 25, 7: 1 << 24}
+    parts, base = [], {}
+    off = 0
+    for rr in rs:
+        n = pool_cw[rr]
+        sr = synth.workload_seed("bench-serve", rr)
+        cw = hm.encode(synth.message_stream_torch(sr, n, rr, dev), n, rr)
+        cw ^= synth.flip_masks_torch(sr, n, rr, 0.1, dev)
+        base[rr] = off
+        off += cw.numel()
+        parts.append(cw)
+    pool = torch.cat(parts)
+    del parts
+    torch.cuda.synchronize()
+    total = n_requests + warm
+    rng = np.random.default_rng(synth.workload_seed("bench-serve-trace", 0) & 0xFFFFFFFF)
+    stream_id = rng.integers(0, 256, size=total)
+    r = (4 + stream_id % 4).astype(np.uint32)
+    sizes = np.floor(256 * np.exp2(10 * rng.random(total))).astype(np.uint64)
+    wpc = np.where(r == 7, 2, 1).astype(np.uint64)
+    offs = np.empty(total, dtype=np.uint64)
+    for rr in rs:
+        m = r == rr
+        span = pool_cw[rr] - sizes[m]
+        offs[m] = np.uint64(base[rr]) + (np.floor(rng.random(m.sum()) * span).astype(np.uint64)) * wpc[m]
+    k = (1 << r.astype(np.int64)) - 1 - r.astype(np.int64)
+    bits = sizes.astype(np.float64) * k
+    # plain-decode time of each request from the plain kernels' algorithmic
+    # bandwidth on its r; the offered load is rho over the mean of these
+    nbytes = np.array([float(n) * algorithmic_bytes_per_codeword(int(x)) for n, x in zip(sizes, r)])
+    t_plain = nbytes / np.array([plain_gBps_per_r[int(x)] for x in r]) / 1e9
+    srv = hm.Server(pool, slots=4, max_batch_packets=4096, max_batch_codewords=1 << 24,
+                    output_pool_bytes=4 << 30, auto_release=True)
+    out = []
+    try:
+        for rho in loads:
+            gaps = rng.exponential(t_plain.mean() / rho, size=total)
+            arrivals = (np.cumsum(gaps) * 1e9).astype(np.uint64)
+            lat, elapsed = srv.run_trace(arrivals, offs, sizes, r, timeout_s=120)
+            done = arrivals.astype(np.float64) + lat.astype(np.float64)
+            # measured window: from the first measured arrival to the last completion
+            window_s = (done[warm:].max() - float(arrivals[warm])) / 1e9
+            span_s = (float(arrivals[-1]) - float(arrivals[warm])) / 1e9
+            lat_us = np.sort(lat[warm:]) / 1e3
+            out.append({
+                "offered_load": rho,
+                "requests": n_requests,
+                "p50_us": round(float(lat_us[len(lat_us) // 2]), 1),
+                "p99_us": round(float(lat_us[int(0.99 * (len(lat_us) - 1))]), 1),
+                "offered_Gbps": round(float(bits[warm:].sum()) / span_s / 1e9, 1),
+                "achieved_Gbps": round(float(bits[warm:].sum()) / window_s / 1e9, 1),
+            })
+    finally:
+        srv.close()
+        del pool
+        torch.cuda.empty_cache()
+    return {"workload": "256 SDR streams, r = 4 + stream % 4, request sizes log-uniform in [256, 2^18] "
+                        "codewords, 10% single-bit errors, Poisson arrivals; 4 batches in flight; output "
+                        "pool 4 GiB", "points": out}
+
+
 def cpu_baseline(log2_sample: int):
     """The oracle on the host cores over a slice of the same workload."""
     import oracle
@@ -122,6 +304,11 @@ def main() -> int:
     ap.add_argument("--log2-cw", type=int, default=WORKLOAD_LOG2)
     ap.add_argument("--cpu-log2", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--batch-packets", type=int, default=20000)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=100000)
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in launch shapes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (counter calibration)")
     args = ap.parse_args()
@@ -144,6 +331,10 @@ def main() -> int:
         print(json.dumps({"copy_bytes": src.numel() * 8, "launches": 5}), flush=True)
         return 0
     hm.library()
+    if not args.no_tune:
+        hm.hamming_tune(None, 3)
+    tuned = {"plain": {r: list(hm.hamming_plain_config_get(r)) for r in range(3, 8)},
+             "batch": list(hm.hamming_batch_config_get())}
     n_cw = 1 << args.log2_cw
     packets = {}
     for r in WORKLOAD_R:
@@ -231,9 +422,17 @@ def main() -> int:
             "avg_launch_us": dom["avg_us"],
         },
         "per_r": per_r,
+        "tuned_shapes": tuned,
     }
     del packets
     torch.cuda.empty_cache()
+    if not args.no_batch:
+        out["batched"] = batched_leg(dev, args.batch_packets, 5)
+    if not args.no_serve:
+        gBps = {x["r"]: x["algorithmic_GBps"] for x in per_r}
+        gBps.setdefault(7, gBps[DOMINANT_R])
+        out["serving"] = serving_leg(dev, gBps, (0.1, 0.3, 0.5, 0.7, 0.9), args.serve_requests,
+                                     max(200, args.serve_requests // 10))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_log2)
     print(json.dumps(out), flush=True)

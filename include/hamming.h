@@ -220,6 +220,26 @@ int hamming_decode_batch(const uint64_t *cw_arena, uint64_t cw_words,
 int hamming_batch_config_set(int schedule, uint32_t xcd_chunk, uint32_t grid_cap_blocks, int use_graph);
 int hamming_batch_config_get(int *schedule, uint32_t *xcd_chunk, uint32_t *grid_cap_blocks, int *use_graph);
 
+/* ---- autotuning ------------------------------------------------------------ */
+
+/*
+ * Autotuner: on the current device and `stream`, time the plain decode of
+ * random 2^26-codeword packets (2^25 for r = 7) for every lane width and XCD
+ * chunking, and the batched decode of a 500-packet batch of mixed sizes and r
+ * for every schedule and XCD chunking; apply the fastest shapes (as
+ * hamming_plain_config_set / hamming_batch_config_set would) and, when
+ * cache_path is neither NULL nor empty, write them there.  flags: bit 0 tunes
+ * the plain decode, bit 1 the batched decode.  Allocates about 1.1 GB of
+ * device memory for the duration of the call and synchronises `stream`.
+ * Returns HAMMING_OK, HAMMING_EINVAL, HAMMING_ENOMEM or HAMMING_EDEVICE.
+ */
+int hamming_tune(const char *cache_path, uint32_t flags, hipStream_t stream);
+
+/* Apply the shapes of a cache written by hamming_tune, if it was written on a
+ * device of the same name and architecture.  Returns HAMMING_OK or
+ * HAMMING_EINVAL (unreadable file, other device, nothing applied). */
+int hamming_tune_load(const char *cache_path);
+
 /* ---- serving: continuous batching of decode requests ---------------------- */
 
 /*

@@ -69,6 +69,8 @@ class hamming_completion(ctypes.Structure):
 
 
 _SIGNATURES.update({
+    "hamming_tune": ([ctypes.c_char_p, ctypes.c_uint32, _vp], _i32),
+    "hamming_tune_load": ([ctypes.c_char_p], _i32),
     "hamming_server_now_ns": ([], _u64),
     "hamming_server_create": ([ctypes.POINTER(hamming_server_config), _vp, _u64, _vp, _u64, ctypes.POINTER(_vp)],
                               _i32),
@@ -308,6 +310,17 @@ class BatchDecoder:
         hamming_decode_batch(self.cw_arena, self.cw_arena.numel(), self.descs_dev, self.n_dev, self.max_packets,
                              max_codewords, self.data, self.data.numel(), self.errpos, self.errpos.numel(), self.status,
                              self.workspace, self.ws_bytes, stream)
+
+
+# ---- autotuning ----------------------------------------------------------------
+
+def hamming_tune(cache_path: str | None = None, flags: int = 3, stream=None) -> None:
+    _check(library().hamming_tune(cache_path.encode() if cache_path else None, flags, _stream(stream)),
+           "hamming_tune")
+
+
+def hamming_tune_load(cache_path: str) -> None:
+    _check(library().hamming_tune_load(cache_path.encode()), "hamming_tune_load")
 
 
 # ---- serving -------------------------------------------------------------------

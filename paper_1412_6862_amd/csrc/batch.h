@@ -46,7 +46,7 @@ struct BatchArgs {
 inline uint32_t batch_coarse_capacity(uint32_t max_packets) { return 2 * max_packets + 1024; }
 inline uint32_t batch_fine_capacity(uint32_t max_packets)
 {
-    return (4 * max_packets > (1u << 22)) ? 4 * max_packets : (1u << 22);
+    return (4 * max_packets > (1u << 24)) ? 4 * max_packets : (1u << 24);
 }
 
 

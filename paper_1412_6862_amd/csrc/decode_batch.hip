@@ -26,10 +26,12 @@
 
 namespace hm {
 
-// Per-r lane widths of a batch schedule.
-template <int U3, int U4, int U5, int U6, int U7>
+// Per-r lane widths of a batch schedule, and the waves per SIMD the decode
+// kernel's register allocation must allow.
+template <int U3, int U4, int U5, int U6, int U7, int WAVES>
 struct Schedule {
     static constexpr int u[5] = {U3, U4, U5, U6, U7};
+    static constexpr int waves_per_simd = WAVES;
     static constexpr int max2(int a, int b) { return a > b ? a : b; }
     static constexpr int LDS_MAX =
         max2(max2(max2(TileShape<3, U3>::LDS_DW, TileShape<4, U4>::LDS_DW),
@@ -39,8 +41,8 @@ struct Schedule {
                   "invalid lane width");
 };
 
-using Sched0 = Schedule<8, 8, 8, 8, 2>;
-using Sched1 = Schedule<8, 4, 4, 4, 2>;
+using Sched0 = Schedule<8, 8, 8, 8, 2, 4>;
+using Sched1 = Schedule<8, 4, 4, 4, 2, 6>;
 
 __device__ __forceinline__ uint64_t message_words(uint64_t n_cw, uint32_t r)
 {
@@ -189,21 +191,26 @@ __device__ __forceinline__ void decode_packet_tile(const hamming_packet& d, uint
 }
 
 template <class S>
-__global__ __launch_bounds__(kBlockThreads) void decode_batch_kernel(BatchArgs a)
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(S::waves_per_simd)))
+void decode_batch_kernel(
+    BatchArgs a, const BatchWs* __restrict__ ws, const uint32_t* __restrict__ fine,
+    const uint64_t* __restrict__ ts, const hamming_packet* __restrict__ descs)
 {
     __shared__ u32x4 lds_raw[kWavesPerBlock][S::LDS_MAX / 4];
-    uint32_t* lds = reinterpret_cast<uint32_t*>(&lds_raw[threadIdx.x >> 6][0]);
-    const uint64_t total = a.ws->total_tiles;
+    // the wave index is uniform: keep tile bookkeeping in scalar registers so
+    // the table and descriptor reads below are scalar loads
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t* lds = reinterpret_cast<uint32_t*>(&lds_raw[wave][0]);
+    const uint64_t total = ws->total_tiles;
     const uint64_t waves = uint64_t(gridDim.x) * kWavesPerBlock;
-    uint64_t t = uint64_t(xcd_block(blockIdx.x, gridDim.x, a.xcd_chunk)) * kWavesPerBlock + (threadIdx.x >> 6);
+    uint64_t t = uint64_t(xcd_block(blockIdx.x, gridDim.x, a.xcd_chunk)) * kWavesPerBlock + wave;
     if (t >= total) return;
-    const uint32_t n = uint32_t(a.ws->n_packets);
-    const uint32_t gf = a.ws->fine_log2;
-    const uint64_t* ts = a.tile_start;
+    const uint32_t n = uint32_t(ws->n_packets);
+    const uint32_t gf = ws->fine_log2;
     for (; t < total; t += waves) {
-        uint32_t p = a.fine[t >> gf];
+        uint32_t p = fine[t >> gf];
         if (gf) p = probe_packet(ts, n, t, p);
-        const hamming_packet d = a.descs[p];
+        const hamming_packet d = descs[p];
         const uint64_t tl = t - ts[p];
         switch (d.r) {
         case 3: decode_packet_tile<3, S::u[0]>(d, tl, a, lds); break;
@@ -227,7 +234,8 @@ static hipError_t launch_batch_s(const BatchArgs& a, uint32_t grid, hipStream_t 
     hipLaunchKernelGGL(batch_fine_kernel, dim3((a.fine_cap + 255) / 256), dim3(256), 0, stream, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((decode_batch_kernel<S>), dim3(grid), dim3(kBlockThreads), 0, stream, a);
+    hipLaunchKernelGGL((decode_batch_kernel<S>), dim3(grid), dim3(kBlockThreads), 0, stream, a, a.ws, a.fine,
+                       a.tile_start, a.descs);
     return hipGetLastError();
 }
 

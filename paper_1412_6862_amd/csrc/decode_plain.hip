@@ -17,7 +17,7 @@ __global__ __launch_bounds__(kBlockThreads) void decode_plain_kernel(
 {
     using T = TileShape<R, U>;
     __shared__ u32x4 lds_raw[kWavesPerBlock][T::LDS_DW / 4];
-    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: scalar bookkeeping
     uint32_t* lds = reinterpret_cast<uint32_t*>(&lds_raw[wave][0]);
     const uint64_t waves = uint64_t(gridDim.x) * kWavesPerBlock;
     // one tile per wave when the grid covers the packet; otherwise waves loop

@@ -8,15 +8,19 @@
 // completion record is queued (and the outputs freed when auto_release).
 // New batches launch whenever a slot is free, so arrivals overlap with
 // batches already on the GPU.
+//
+// Every per-request step is O(1): requests live in a ring indexed by id,
+// admission is FIFO so a batch is a contiguous id range, and outputs come
+// from a ring allocator over the output pool that reclaims space in id
+// order (a request released early keeps its space until every older request
+// is released too).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
 
 #include <chrono>
 #include <deque>
-#include <map>
 #include <new>
-#include <unordered_map>
 #include <vector>
 
 #include "hamming.h"
@@ -27,85 +31,86 @@ constexpr uint64_t kAlign = 256;   // output allocations start on 256-byte bound
 
 uint64_t round_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
-// First-fit allocator over [0, size) with coalescing frees.
-class RangeAllocator {
-public:
-    explicit RangeAllocator(uint64_t size) : size_(size) { if (size) free_[0] = size; }
-
-    bool alloc(uint64_t bytes, uint64_t* off)
-    {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const uint64_t rest = it->second - bytes;
-                const uint64_t start = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[start] = rest;
-                used_ += bytes;
-                return true;
-            }
-        }
-        return false;
-    }
-
-    void release(uint64_t off, uint64_t bytes)
-    {
-        used_ -= bytes;
-        auto next = free_.lower_bound(off);
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == off) {
-                off = prev->first;
-                bytes += prev->second;
-                free_.erase(prev);
-            }
-        }
-        next = free_.lower_bound(off);
-        if (next != free_.end() && off + bytes == next->first) {
-            bytes += next->second;
-            free_.erase(next);
-        }
-        free_[off] = bytes;
-    }
-
-    uint64_t used() const { return used_; }
-    uint64_t size() const { return size_; }
-
-private:
-    uint64_t size_;
-    uint64_t used_ = 0;
-    std::map<uint64_t, uint64_t> free_;
-};
-
-struct Request {
-    uint64_t in_word_off, n_cw;
-    uint32_t r;
-    uint64_t arrival_ns;
-    uint64_t out_off = 0, out_bytes = 0;
-    uint64_t data_bytes = 0;
-    bool done = false;
-};
-
-struct Slot {
-    hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
-    unsigned char* host = nullptr;     // pinned: n_packets (uint32, padded to 8) + descriptors
-    hamming_packet* descs_dev = nullptr;
-    uint32_t* n_dev = nullptr;
-    int32_t* status_dev = nullptr;
-    int32_t* status_host = nullptr;    // pinned
-    void* ws = nullptr;
-    uint64_t ws_bytes = 0;
-    std::vector<uint64_t> reqs;
-    bool busy = false;
-};
-
 uint64_t now_ns()
 {
     return uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(
                         std::chrono::steady_clock::now().time_since_epoch())
                         .count());
 }
+
+enum : uint8_t { kQueued = 0, kInflight = 1, kDone = 2, kReleased = 3 };
+
+struct Request {
+    uint64_t in_word_off, n_cw;
+    uint64_t arrival_ns;
+    uint64_t out_off, out_bytes, data_bytes;
+    uint32_t r;
+    uint8_t state;
+};
+
+// Circular allocator over [0, size): allocations are handed out and
+// reclaimed in the same (FIFO) order.  head == tail with live allocations
+// means full.
+class RingAllocator {
+public:
+    explicit RingAllocator(uint64_t size = 0) : size_(size) {}
+
+    bool alloc(uint64_t bytes, uint64_t* off)
+    {
+        if (live_ == 0) head_ = tail_ = 0;
+        if (bytes == 0 || bytes > size_) return false;
+        if (live_ == 0 || head_ > tail_) {              // free space: [head, size) and [0, tail)
+            if (size_ - head_ >= bytes) {
+                *off = head_;
+                head_ += bytes;
+            } else if (tail_ >= bytes) {                // wrap; [head, size) is skipped
+                *off = 0;
+                head_ = bytes;
+            } else {
+                return false;
+            }
+        } else {                                        // wrapped: free space is [head, tail)
+            if (tail_ - head_ < bytes) return false;
+            *off = head_;
+            head_ += bytes;
+        }
+        ++live_;
+        used_ += bytes;
+        return true;
+    }
+
+    // Reclaim the oldest live allocation.
+    void release_oldest(uint64_t off, uint64_t bytes)
+    {
+        tail_ = off + bytes;
+        --live_;
+        used_ -= bytes;
+        if (live_ == 0) head_ = tail_ = 0;
+    }
+
+    uint64_t size() const { return size_; }
+    uint64_t used() const { return used_; }
+
+private:
+    uint64_t size_;
+    uint64_t head_ = 0, tail_ = 0, used_ = 0, live_ = 0;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    unsigned char* host = nullptr;     // pinned: n_packets (uint32, padded to 8) + descriptors
+    uint32_t* n_dev = nullptr;         // device: n_packets then the descriptors
+    hamming_packet* descs_dev = nullptr;
+    void* ws = nullptr;
+    uint64_t ws_bytes = 0;
+    uint64_t first = 0, count = 0;     // request ids [first, first + count)
+    bool busy = false;
+};
+
+// Grid-size hints (codewords) below the largest batch: one graph per tier per
+// slot, so a small batch does not launch the grid of the largest one.
+constexpr uint64_t kTiers[] = {uint64_t(1) << 18, uint64_t(1) << 21};
 
 }  // namespace
 
@@ -114,19 +119,26 @@ struct hamming_server {
     const uint64_t* pool = nullptr;
     uint64_t pool_words = 0;
     unsigned char* out_base = nullptr;
-    RangeAllocator alloc{0};
+    RingAllocator alloc;
     std::vector<Slot> slots;
-    std::deque<uint64_t> queue;
-    std::unordered_map<uint64_t, Request> reqs;
+    std::vector<Request> ring;         // request id -> ring[id % ring.size()]
+    uint64_t next_id = 0;              // ids [next_admit, next_id) are queued
+    uint64_t next_admit = 0;
+    uint64_t oldest_live = 0;          // smallest id not yet released
     std::deque<hamming_completion> completions;
-    uint64_t next_id = 0;
     uint64_t inflight = 0;
     uint64_t batches = 0;
+
+    Request& req(uint64_t id) { return ring[id % ring.size()]; }
 };
 
 namespace {
 
-int message_bits(uint32_t r) { return (1 << r) - 1 - int(r); }
+uint64_t message_bytes(uint64_t n_cw, uint32_t r)
+{
+    const uint64_t k = (uint64_t(1) << r) - 1 - r;
+    return ((n_cw * k + 63) / 64) * 8;
+}
 
 void free_server(hamming_server* s)
 {
@@ -134,16 +146,24 @@ void free_server(hamming_server* s)
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.host) (void)hipHostFree(sl.host);
-        if (sl.status_host) (void)hipHostFree(sl.status_host);
         if (sl.n_dev) (void)hipFree(sl.n_dev);          // also holds descs_dev
-        if (sl.status_dev) (void)hipFree(sl.status_dev);
         if (sl.ws) (void)hipFree(sl.ws);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
     delete s;
 }
 
-// Record completions of slots whose batch finished.
+// Reclaim output space of released requests, oldest first.
+void reclaim(hamming_server* s)
+{
+    while (s->oldest_live < s->next_admit) {
+        Request& rq = s->req(s->oldest_live);
+        if (rq.state != kReleased) break;
+        s->alloc.release_oldest(rq.out_off, rq.out_bytes);
+        ++s->oldest_live;
+    }
+}
+
 int reap(hamming_server* s)
 {
     for (auto& sl : s->slots) {
@@ -152,45 +172,42 @@ int reap(hamming_server* s)
         if (q == hipErrorNotReady) continue;
         if (q != hipSuccess) return HAMMING_EDEVICE;
         const uint64_t t = now_ns();
-        for (size_t i = 0; i < sl.reqs.size(); ++i) {
-            const uint64_t id = sl.reqs[i];
-            Request& rq = s->reqs[id];
-            rq.done = true;
+        for (uint64_t id = sl.first; id < sl.first + sl.count; ++id) {
+            Request& rq = s->req(id);
             hamming_completion c;
-            memset(&c, 0, sizeof c);
             c.request_id = id;
             c.data_offset = rq.out_off;
             c.errpos_offset = rq.out_off + round_up(rq.data_bytes, 16);
             c.submit_ns = rq.arrival_ns;
             c.complete_ns = t;
-            c.status = sl.status_host[i];
+            c.status = HAMMING_OK;
+            c.reserved = 0;
             s->completions.push_back(c);
-            if (s->cfg.auto_release) {
-                s->alloc.release(rq.out_off, rq.out_bytes);
-                s->reqs.erase(id);
-            }
+            rq.state = s->cfg.auto_release ? kReleased : kDone;
         }
-        s->inflight -= sl.reqs.size();
-        sl.reqs.clear();
+        s->inflight -= sl.count;
         sl.busy = false;
+        sl.count = 0;
     }
+    if (s->cfg.auto_release) reclaim(s);
     return HAMMING_OK;
 }
 
-// Fill free slots with admitted requests and launch them.
 int launch(hamming_server* s)
 {
     for (auto& sl : s->slots) {
-        if (sl.busy || s->queue.empty()) continue;
+        if (sl.busy || s->next_admit == s->next_id) continue;
+        auto* descs = reinterpret_cast<hamming_packet*>(sl.host + 8);
         uint32_t n = 0;
         uint64_t cws = 0;
-        auto* descs = reinterpret_cast<hamming_packet*>(sl.host + 8);
-        while (!s->queue.empty() && n < s->cfg.max_batch_packets) {
-            Request& rq = s->reqs[s->queue.front()];
+        const uint64_t first = s->next_admit;
+        while (s->next_admit < s->next_id && n < s->cfg.max_batch_packets) {
+            Request& rq = s->req(s->next_admit);
             if (n > 0 && cws + rq.n_cw > s->cfg.max_batch_codewords) break;
             uint64_t off = 0;
-            if (!s->alloc.alloc(rq.out_bytes, &off)) break;      // wait for memory (FIFO)
+            if (!s->alloc.alloc(rq.out_bytes, &off)) break;     // wait for memory (FIFO)
             rq.out_off = off;
+            rq.state = kInflight;
             hamming_packet& d = descs[n];
             d.in_word_off = rq.in_word_off;
             d.n_cw = rq.n_cw;
@@ -198,28 +215,29 @@ int launch(hamming_server* s)
             d.flags = 0;
             d.data_word_off = off / 8;
             d.errpos_off = off + round_up(rq.data_bytes, 16);
-            sl.reqs.push_back(s->queue.front());
-            s->queue.pop_front();
+            ++s->next_admit;
             cws += rq.n_cw;
             ++n;
         }
-        if (n == 0) break;                                       // head of the queue does not fit
+        if (n == 0) break;                                      // the head of the queue does not fit
         *reinterpret_cast<uint32_t*>(sl.host) = n;
-        const uint64_t bytes = 8 + uint64_t(n) * sizeof(hamming_packet);
-        // n_packets and the descriptors travel in one copy (n_dev sits just
-        // before descs_dev in the same device allocation).
-        if (hipMemcpyAsync(sl.n_dev, sl.host, bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
-            return HAMMING_EDEVICE;
-        const int rc = hamming_decode_batch(s->pool, s->pool_words, sl.descs_dev, sl.n_dev,
-                                            s->cfg.max_batch_packets, s->cfg.max_batch_codewords,
-                                            reinterpret_cast<uint64_t*>(s->out_base), s->alloc.size() / 8,
-                                            s->out_base, s->alloc.size(), sl.status_dev, sl.ws, sl.ws_bytes,
-                                            sl.stream);
-        if (rc != HAMMING_OK) return rc;
-        if (hipMemcpyAsync(sl.status_host, sl.status_dev, sizeof(int32_t) * n, hipMemcpyDeviceToHost,
+        if (hipMemcpyAsync(sl.n_dev, sl.host, 8 + uint64_t(n) * sizeof(hamming_packet), hipMemcpyHostToDevice,
                            sl.stream) != hipSuccess)
             return HAMMING_EDEVICE;
+        uint64_t hint = s->cfg.max_batch_codewords;
+        for (uint64_t tier : kTiers)
+            if (cws <= tier && tier < hint) {
+                hint = tier;
+                break;
+            }
+        const int rc = hamming_decode_batch(s->pool, s->pool_words, sl.descs_dev, sl.n_dev,
+                                            s->cfg.max_batch_packets, hint, reinterpret_cast<uint64_t*>(s->out_base),
+                                            s->alloc.size() / 8, s->out_base, s->alloc.size(), nullptr, sl.ws,
+                                            sl.ws_bytes, sl.stream);
+        if (rc != HAMMING_OK) return rc;
         if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return HAMMING_EDEVICE;
+        sl.first = first;
+        sl.count = n;
         sl.busy = true;
         s->inflight += n;
         ++s->batches;
@@ -251,7 +269,14 @@ int hamming_server_create(const hamming_server_config* config, const uint64_t* c
     s->pool = cw_pool;
     s->pool_words = cw_pool_words;
     s->out_base = static_cast<unsigned char*>(output_pool);
-    s->alloc = RangeAllocator(output_pool_bytes / kAlign * kAlign);
+    s->alloc = RingAllocator(output_pool_bytes / kAlign * kAlign);
+    try {
+        // queued + in flight + completed but not yet released
+        s->ring.resize(uint64_t(c.max_queue) + uint64_t(c.slots) * c.max_batch_packets);
+    } catch (...) {
+        delete s;
+        return HAMMING_ENOMEM;
+    }
     s->slots.resize(c.slots);
     const uint64_t ws_bytes = hamming_batch_workspace_bytes(c.max_batch_packets);
     for (auto& sl : s->slots) {
@@ -260,14 +285,11 @@ int hamming_server_create(const hamming_server_config* config, const uint64_t* c
         bool ok = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
                   hipHostMalloc(reinterpret_cast<void**>(&sl.host), dbytes, hipHostMallocDefault) == hipSuccess &&
-                  hipHostMalloc(reinterpret_cast<void**>(&sl.status_host), 4ull * c.max_batch_packets,
-                                hipHostMallocDefault) == hipSuccess &&
                   hipMalloc(reinterpret_cast<void**>(&dev), dbytes) == hipSuccess;
         if (ok) {
             sl.n_dev = reinterpret_cast<uint32_t*>(dev);
             sl.descs_dev = reinterpret_cast<hamming_packet*>(dev + 8);
-            ok = hipMalloc(reinterpret_cast<void**>(&sl.status_dev), 4ull * c.max_batch_packets) == hipSuccess &&
-                 hipMalloc(&sl.ws, ws_bytes) == hipSuccess;
+            ok = hipMalloc(&sl.ws, ws_bytes) == hipSuccess;
             sl.ws_bytes = ws_bytes;
         }
         if (!ok) {
@@ -295,22 +317,22 @@ int hamming_server_submit(hamming_server* s, uint64_t in_word_off, uint64_t n_cw
     const uint64_t wpc = r == 7 ? 2 : 1;
     if (n_cw > HAMMING_MAX_CODEWORDS || in_word_off > s->pool_words || n_cw * wpc > s->pool_words - in_word_off)
         return HAMMING_ERANGE;
-    const uint64_t data_bytes = ((n_cw * uint64_t(message_bits(r)) + 63) / 64) * 8;
+    const uint64_t data_bytes = message_bytes(n_cw, r);
     uint64_t out_bytes = round_up(round_up(data_bytes, 16) + n_cw, kAlign);
     if (out_bytes == 0) out_bytes = kAlign;                      // every request owns a range
-    if (out_bytes > s->alloc.size()) return HAMMING_ERANGE;
-    if (s->queue.size() >= s->cfg.max_queue) return HAMMING_ENOMEM;
-    Request rq;
+    if (out_bytes >= s->alloc.size()) return HAMMING_ERANGE;
+    if (s->next_id - s->next_admit >= s->cfg.max_queue || s->next_id - s->oldest_live >= s->ring.size())
+        return HAMMING_ENOMEM;
+    Request& rq = s->req(s->next_id);
     rq.in_word_off = in_word_off;
     rq.n_cw = n_cw;
-    rq.r = r;
     rq.arrival_ns = arrival_ns;
-    rq.data_bytes = data_bytes;
+    rq.out_off = 0;
     rq.out_bytes = out_bytes;
-    const uint64_t id = s->next_id++;
-    s->reqs.emplace(id, rq);
-    s->queue.push_back(id);
-    *request_id = id;
+    rq.data_bytes = data_bytes;
+    rq.r = r;
+    rq.state = kQueued;
+    *request_id = s->next_id++;
     return HAMMING_OK;
 }
 
@@ -336,11 +358,11 @@ int hamming_server_poll(hamming_server* s, hamming_completion* out, uint32_t max
 
 int hamming_server_release(hamming_server* s, uint64_t request_id)
 {
-    if (!s) return HAMMING_EINVAL;
-    auto it = s->reqs.find(request_id);
-    if (it == s->reqs.end() || !it->second.done) return HAMMING_EINVAL;
-    s->alloc.release(it->second.out_off, it->second.out_bytes);
-    s->reqs.erase(it);
+    if (!s || request_id < s->oldest_live || request_id >= s->next_admit) return HAMMING_EINVAL;
+    Request& rq = s->req(request_id);
+    if (rq.state != kDone) return HAMMING_EINVAL;
+    rq.state = kReleased;
+    reclaim(s);
     return HAMMING_OK;
 }
 
@@ -355,7 +377,7 @@ int hamming_server_output_pool(hamming_server* s, void** base, uint64_t* bytes)
 int hamming_server_stats(hamming_server* s, uint64_t* queued, uint64_t* inflight, uint64_t* used, uint64_t* batches)
 {
     if (!s || !queued || !inflight || !used || !batches) return HAMMING_EINVAL;
-    *queued = s->queue.size();
+    *queued = s->next_id - s->next_admit;
     *inflight = s->inflight;
     *used = s->alloc.used();
     *batches = s->batches;
@@ -369,9 +391,8 @@ int hamming_server_run_trace(hamming_server* s, uint32_t n, const uint64_t* arri
     if (!s || !s->cfg.auto_release || (n && (!arrival_ns || !in_word_off || !n_cw || !r || !latency_ns)) ||
         !elapsed_ns)
         return HAMMING_EINVAL;
-    std::unordered_map<uint64_t, uint32_t> index;   // request id -> trace position
-    index.reserve(n * 2 + 1);
-    std::vector<hamming_completion> buf(1024);
+    s->completions.clear();
+    const uint64_t first_id = s->next_id;             // trace request i gets id first_id + i
     const uint64_t start = now_ns();
     uint32_t next = 0, finished = 0;
     while (finished < n) {
@@ -381,24 +402,20 @@ int hamming_server_run_trace(hamming_server* s, uint32_t n, const uint64_t* arri
             uint64_t id = 0;
             const int rc = hamming_server_submit(s, in_word_off[next], n_cw[next], r[next], start + arrival_ns[next],
                                                  &id);
+            if (rc == HAMMING_ENOMEM) break;            // queue full: retry after progress
             if (rc != HAMMING_OK) return rc;
-            index[id] = next;
             ++next;
         }
-        int rc = hamming_server_progress(s);
+        const int rc = hamming_server_progress(s);
         if (rc != HAMMING_OK) return rc;
-        uint32_t got = 0;
-        do {
-            rc = hamming_server_poll(s, buf.data(), uint32_t(buf.size()), &got);
-            if (rc != HAMMING_OK) return rc;
-            for (uint32_t i = 0; i < got; ++i) {
-                auto it = index.find(buf[i].request_id);
-                if (it == index.end()) continue;          // a request submitted before this trace
-                latency_ns[it->second] = buf[i].complete_ns - buf[i].submit_ns;
-                index.erase(it);
+        while (!s->completions.empty()) {
+            const hamming_completion& c = s->completions.front();
+            if (c.request_id >= first_id && c.request_id - first_id < n) {
+                latency_ns[c.request_id - first_id] = c.complete_ns - c.submit_ns;
                 ++finished;
             }
-        } while (got == buf.size());
+            s->completions.pop_front();
+        }
     }
     *elapsed_ns = now_ns() - start;
     return HAMMING_OK;

@@ -1,0 +1,234 @@
+// Autotuner: measures the launch shapes of the plain and batched decode on
+// the current device, keeps the fastest, and persists them to a text cache
+// (one JSON object per line) that hamming_tune_load applies in later runs.
+// Tuning inputs are random words: decode time does not depend on the data.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "hamming.h"
+
+namespace {
+
+__global__ void fill_random_kernel(uint64_t* p, uint64_t n, uint64_t seed)
+{
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;   // SplitMix64 output function
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        p[i] = z ^ (z >> 31);
+    }
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
+// Average milliseconds of `reps` calls of fn after `warm` warm-up calls.
+template <class F>
+int time_ms(hipStream_t s, int warm, int reps, F fn, float* ms)
+{
+    for (int i = 0; i < warm; ++i)
+        if (fn() != HAMMING_OK) return HAMMING_EDEVICE;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return HAMMING_EDEVICE;
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return HAMMING_EDEVICE; }
+    int rc = HAMMING_OK;
+    if (hipEventRecord(a, s) != hipSuccess) rc = HAMMING_EDEVICE;
+    for (int i = 0; i < reps && rc == HAMMING_OK; ++i) rc = fn();
+    if (rc == HAMMING_OK && (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                             hipEventElapsedTime(ms, a, b) != hipSuccess))
+        rc = HAMMING_EDEVICE;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc == HAMMING_OK) *ms /= float(reps);
+    return rc;
+}
+
+struct PlainChoice {
+    int u;
+    uint64_t max_blocks;
+    uint32_t xcd_chunk;
+    float us;
+};
+
+struct BatchChoice {
+    int schedule;
+    uint32_t xcd_chunk, grid_cap;
+    int use_graph;
+    float ms;
+};
+
+std::string device_name()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string s = std::string(prop.name) + " " + prop.gcnArchName;
+    for (auto& c : s)
+        if (c == '"' || c == '\\' || c == '\n') c = ' ';
+    return s;
+}
+
+constexpr uint32_t kXcdChoices[] = {1, 8, 32, 128};
+
+}  // namespace
+
+extern "C" {
+
+int hamming_tune(const char* cache_path, uint32_t flags, hipStream_t stream)
+{
+    const bool do_plain = (flags & 1u) != 0, do_batch = (flags & 2u) != 0;
+    if (!do_plain && !do_batch) return HAMMING_EINVAL;
+    const uint64_t n6 = uint64_t(1) << 26;              // codewords per plain trial (2^25 for r = 7)
+    DevBuf cw, data, ep, ws, descs_dev;
+    if (hipMalloc(&cw.p, n6 * 8) != hipSuccess || hipMalloc(&data.p, n6 * 8) != hipSuccess ||
+        hipMalloc(&ep.p, n6) != hipSuccess) {
+        (void)hipGetLastError();
+        return HAMMING_ENOMEM;
+    }
+    hipLaunchKernelGGL(fill_random_kernel, dim3(4096), dim3(256), 0, stream, static_cast<uint64_t*>(cw.p), n6,
+                       0x14126862ull);
+    if (hipGetLastError() != hipSuccess) return HAMMING_EDEVICE;
+
+    std::vector<PlainChoice> plain(5);
+    for (int r = 3; r <= 7; ++r) {
+        int u0;
+        uint64_t mb0;
+        uint32_t xc0;
+        hamming_plain_config_get(r, &u0, &mb0, &xc0);
+        plain[r - 3] = {u0, mb0, xc0, 0.0f};
+        if (!do_plain) continue;
+        const uint64_t n = r == 7 ? n6 / 2 : n6;
+        float best = 1e30f;
+        for (int u : {2, 4, 8, 16}) {
+            for (uint32_t xc : kXcdChoices) {
+                if (hamming_plain_config_set(r, u, 0, xc) != HAMMING_OK) continue;   // invalid lane width
+                float ms = 0;
+                const int rc = time_ms(stream, 2, 5, [&] {
+                    return hamming_decode(static_cast<const uint64_t*>(cw.p), n, r, data.p,
+                                          static_cast<uint8_t*>(ep.p), stream);
+                }, &ms);
+                if (rc != HAMMING_OK) return rc;
+                if (ms < best) {
+                    best = ms;
+                    plain[r - 3] = {u, 0, xc, ms * 1000.0f};
+                }
+            }
+        }
+        hamming_plain_config_set(r, plain[r - 3].u, plain[r - 3].max_blocks, plain[r - 3].xcd_chunk);
+    }
+
+    BatchChoice batch;
+    {
+        uint32_t xc0, cap0;
+        hamming_batch_config_get(&batch.schedule, &xc0, &cap0, &batch.use_graph);
+        batch.xcd_chunk = xc0;
+        batch.grid_cap = cap0;
+        batch.ms = 0;
+    }
+    if (do_batch) {
+        // 500 packets, sizes log-uniform in [64, 2^18] codewords, r uniform in 3..7
+        const uint32_t np = 500;
+        std::vector<hamming_packet> d(np);
+        uint64_t state = 0x6862ull, off = 0, total = 0;
+        auto next = [&] {
+            state = state * 6364136223846793005ull + 1442695040888963407ull;
+            return double(state >> 11) / 9007199254740992.0;
+        };
+        for (uint32_t i = 0; i < np; ++i) {
+            d[i].n_cw = uint64_t(64.0 * std::exp2(12.0 * next()));
+            d[i].r = 3 + uint32_t(5.0 * next()) % 5;
+            d[i].flags = 0;
+            d[i].in_word_off = off;
+            off += d[i].n_cw * (d[i].r == 7 ? 2 : 1);
+            total += d[i].n_cw;
+        }
+        uint64_t dw = 0, eb = 0;
+        int rc = hamming_batch_layout(d.data(), np, &dw, &eb);
+        if (rc != HAMMING_OK) return rc;
+        if (off > n6 || dw > n6 || eb > n6) return HAMMING_ERANGE;
+        const uint64_t wsb = hamming_batch_workspace_bytes(np);
+        if (hipMalloc(&ws.p, wsb) != hipSuccess || hipMalloc(&descs_dev.p, np * sizeof(hamming_packet) + 8) != hipSuccess) {
+            (void)hipGetLastError();
+            return HAMMING_ENOMEM;
+        }
+        uint32_t* n_dev = static_cast<uint32_t*>(descs_dev.p);
+        auto* dd = reinterpret_cast<hamming_packet*>(static_cast<char*>(descs_dev.p) + 8);
+        if (hipMemcpy(dd, d.data(), np * sizeof(hamming_packet), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(n_dev, &np, 4, hipMemcpyHostToDevice) != hipSuccess)
+            return HAMMING_EDEVICE;
+        float best = 1e30f;
+        for (int sched : {0, 1}) {
+            for (uint32_t xc : kXcdChoices) {
+                // direct launches while tuning: no graph is cached for these scratch buffers
+                if (hamming_batch_config_set(sched, xc, 0, 0) != HAMMING_OK) return HAMMING_EINVAL;
+                float ms = 0;
+                rc = time_ms(stream, 2, 5, [&] {
+                    return hamming_decode_batch(static_cast<const uint64_t*>(cw.p), off, dd, n_dev, np, total,
+                                                static_cast<uint64_t*>(data.p), dw, static_cast<uint8_t*>(ep.p), eb,
+                                                nullptr, ws.p, wsb, stream);
+                }, &ms);
+                if (rc != HAMMING_OK) return rc;
+                if (ms < best) {
+                    best = ms;
+                    batch = {sched, xc, 0, 1, ms};
+                }
+            }
+        }
+        hamming_batch_config_set(batch.schedule, batch.xcd_chunk, batch.grid_cap, batch.use_graph);
+    }
+
+    if (cache_path && *cache_path) {
+        FILE* f = fopen(cache_path, "w");
+        if (!f) return HAMMING_EINVAL;
+        fprintf(f, "{\"device\": \"%s\"}\n", device_name().c_str());
+        for (int r = 3; r <= 7; ++r) {
+            const PlainChoice& c = plain[r - 3];
+            fprintf(f, "{\"plain\": %d, \"lane_codewords\": %d, \"max_blocks\": %llu, \"xcd_chunk\": %u, \"us\": %.2f}\n",
+                    r, c.u, (unsigned long long)c.max_blocks, c.xcd_chunk, c.us);
+        }
+        fprintf(f, "{\"batch\": %d, \"xcd_chunk\": %u, \"grid_cap_blocks\": %u, \"use_graph\": %d, \"ms\": %.3f}\n",
+                batch.schedule, batch.xcd_chunk, batch.grid_cap, batch.use_graph, batch.ms);
+        fclose(f);
+    }
+    return HAMMING_OK;
+}
+
+int hamming_tune_load(const char* cache_path)
+{
+    if (!cache_path) return HAMMING_EINVAL;
+    FILE* f = fopen(cache_path, "r");
+    if (!f) return HAMMING_EINVAL;
+    char line[512];
+    bool device_ok = false;
+    int applied = 0;
+    const std::string me = device_name();
+    while (fgets(line, sizeof line, f)) {
+        char name[256];
+        int r, u, sched, graph;
+        unsigned long long mb;
+        unsigned xc, cap;
+        if (sscanf(line, "{\"device\": \"%255[^\"]\"}", name) == 1) {
+            device_ok = me == name;
+        } else if (device_ok &&
+                   sscanf(line, "{\"plain\": %d, \"lane_codewords\": %d, \"max_blocks\": %llu, \"xcd_chunk\": %u", &r,
+                          &u, &mb, &xc) == 4) {
+            if (hamming_plain_config_set(r, u, mb, xc) == HAMMING_OK) ++applied;
+        } else if (device_ok && sscanf(line, "{\"batch\": %d, \"xcd_chunk\": %u, \"grid_cap_blocks\": %u, \"use_graph\": %d",
+                                       &sched, &xc, &cap, &graph) == 4) {
+            if (hamming_batch_config_set(sched, xc, cap, graph) == HAMMING_OK) ++applied;
+        }
+    }
+    fclose(f);
+    return applied > 0 ? HAMMING_OK : HAMMING_EINVAL;
+}
+
+}  // extern "C"

@@ -196,6 +196,86 @@ def padding_garbage(seed: int, n_cw: int, r: int) -> np.ndarray:
     return g.reshape(-1)
 
 
+# --- the same generator on torch tensors (CPU or GPU) --------------------------
+#
+# Identical bits to the numpy functions above: int64 arithmetic wraps modulo
+# 2^64 exactly like uint64, and logical right shifts are masked arithmetic
+# shifts.  Used to synthesise workloads too large to build on the host.
+
+def _to_i64(v: int) -> int:
+    v &= _MASK64
+    return v - (1 << 64) if v >= (1 << 63) else v
+
+
+def _srl(x, s: int):
+    import torch
+
+    return torch.bitwise_and(torch.bitwise_right_shift(x, s), _to_i64((1 << (64 - s)) - 1))
+
+
+def mix64_torch(z):
+    z = torch_mul(torch_xor(z, _srl(z, 30)), 0xBF58476D1CE4E5B9)
+    z = torch_mul(torch_xor(z, _srl(z, 27)), 0x94D049BB133111EB)
+    return torch_xor(z, _srl(z, 31))
+
+
+def torch_xor(a, b):
+    import torch
+
+    return torch.bitwise_xor(a, b)
+
+
+def torch_mul(a, c: int):
+    return a * _to_i64(c)
+
+
+def draws_torch(seed: int, start: int, count: int, device):
+    """Draws start .. start+count-1 of the stream seeded with ``seed`` as an
+    int64 tensor on ``device`` (bit-identical to ``draws``)."""
+    import torch
+
+    ctr = torch.arange(start + 1, start + count + 1, dtype=torch.int64, device=device)
+    state = ctr * _to_i64(0x9E3779B97F4A7C15) + _to_i64(seed)
+    return mix64_torch(state)
+
+
+def message_stream_torch(seed: int, n_cw: int, r: int, device):
+    """``message_stream`` as an int64 tensor on ``device``."""
+    _, k, _ = code_sizes(r)
+    bits = n_cw * k
+    nwords = (bits + 63) // 64
+    out = draws_torch(seed, 0, nwords, device)
+    tail = bits % 64
+    if nwords and tail:
+        out[-1] &= _to_i64((1 << tail) - 1)
+    return out
+
+
+def flip_masks_torch(seed: int, n_cw: int, r: int, p_single, device):
+    """Single-flip masks (storage layout, int64, n_cw*WPC words) with the same
+    draws as ``error_positions(seed, n_cw, r, p_single)``; ``p_single`` may be a
+    per-codeword float64 tensor (a packet-wise rate) or a number."""
+    import torch
+
+    n, _, wpc = code_sizes(r)
+    u = _srl(draws_torch(subseed(seed, "kind"), 0, n_cw, device), 11)
+    if isinstance(p_single, (int, float)):
+        thr = torch.full((n_cw,), _threshold(float(p_single)), dtype=torch.int64, device=device)
+    else:
+        thr = torch.floor(p_single.to(torch.float64) * float(1 << 53)).to(torch.int64)
+    hit = u < thr
+    v = draws_torch(subseed(seed, "pos"), 0, n_cw, device)
+    pos = 1 + torch.bitwise_right_shift(_srl(v, 32) * n, 32)          # (v >> 32) * n < 2^39
+    bit = pos - 1
+    masks = torch.zeros((n_cw, wpc), dtype=torch.int64, device=device)
+    one = torch.ones_like(bit)
+    for w in range(wpc):
+        in_w = hit & (torch.div(bit, 64, rounding_mode="floor") == w)
+        val = torch.bitwise_left_shift(one, torch.remainder(bit, 64))
+        masks[:, w] = torch.where(in_w, val, torch.zeros_like(val))
+    return masks.reshape(-1)
+
+
 # --- workload recipes ------------------------------------------------------
 
 PLAIN_ERROR_RATES = (0.0, 0.01, 0.1, 0.5, 1.0)

@@ -126,7 +126,7 @@ def test_batch_layout_host_helper():
 def test_batch_workspace_and_validation_codes():
     lib = hm.library()
     assert hm.hamming_batch_workspace_bytes(0) >= 64
-    assert hm.hamming_batch_workspace_bytes(1000) >= 64 + 8 * 1001 + 4 * 3024 + 4 * (1 << 22)
+    assert hm.hamming_batch_workspace_bytes(1000) >= 64 + 8 * 1001 + 4 * 3024 + 4 * (1 << 24)
     assert hm.hamming_batch_workspace_bytes(hm.HAMMING_MAX_BATCH + 1) == 0
     A = 1 << 20
     ws = hm.hamming_batch_workspace_bytes(10)

@@ -176,3 +176,29 @@ def test_encode_parity(gpu_device, r, n_cw):
     out = hm.encode(to_device(stream, gpu_device), n_cw, r)
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy().view(np.uint64), ref)
+
+
+def test_tuner_applies_and_persists_valid_shapes(gpu_device, tmp_path):
+    import torch
+
+    old_plain = {r: hm.hamming_plain_config_get(r) for r in range(3, 8)}
+    old_batch = hm.hamming_batch_config_get()
+    path = str(tmp_path / "tune.json")
+    try:
+        hm.hamming_tune(path, 3)
+        torch.cuda.synchronize()
+        text = open(path).read()
+        assert '"device"' in text and text.count('"plain"') == 5 and '"batch"' in text
+        tuned = {r: hm.hamming_plain_config_get(r) for r in range(3, 8)}
+        for r in range(3, 8):
+            hm.hamming_plain_config_set(r, *old_plain[r])
+        hm.hamming_tune_load(path)
+        assert {r: hm.hamming_plain_config_get(r) for r in range(3, 8)} == tuned
+        # decoding with the tuned shapes is still exact
+        for r in (3, 6, 7):
+            y = received_words(synth.workload_seed("gpu-tuned", r), 5000, r, p_single=0.5)
+            _check(y, r, gpu_device)
+    finally:
+        for r in range(3, 8):
+            hm.hamming_plain_config_set(r, *old_plain[r])
+        hm.hamming_batch_config_set(*old_batch)

@@ -80,3 +80,23 @@ def test_batch_packets_recipe():
     assert p.min() >= 0 and p.max() <= 0.5
     med = np.median(np.log2(n_cw))
     assert abs(med - 13) < 0.2
+
+
+def test_torch_generator_matches_numpy_bit_for_bit():
+    import torch
+
+    for seed in (1, 1234567, synth.BASE_SEED):
+        a = synth.draws(seed, 5, 3000)
+        b = synth.draws_torch(seed, 5, 3000, torch.device("cpu")).numpy().view(np.uint64)
+        assert np.array_equal(a, b)
+    for r in (3, 6, 7):
+        s1 = synth.message_stream(9, 777, r)
+        s2 = synth.message_stream_torch(9, 777, r, torch.device("cpu")).numpy().view(np.uint64)
+        assert np.array_equal(s1, s2)
+        p1, p2 = synth.error_positions(4, 5000, r, p_single=0.3)
+        m1 = synth.flip_masks(p1, p2, r)
+        m2 = synth.flip_masks_torch(4, 5000, r, 0.3, torch.device("cpu")).numpy().view(np.uint64)
+        assert np.array_equal(m1, m2)
+        rates = torch.full((5000,), 0.3, dtype=torch.float64)
+        m3 = synth.flip_masks_torch(4, 5000, r, rates, torch.device("cpu")).numpy().view(np.uint64)
+        assert np.array_equal(m1, m3)
