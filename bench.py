@@ -29,6 +29,7 @@ WORKLOAD_LOG2 = 26
 P_SINGLE = 0.1
 DOMINANT_R = 6
 PROFILE_GLOB = os.path.join(ROOT, "profiles", "decode_plain_r6_2p26_traffic.md")
+TUNED_SHAPES = os.path.join(ROOT, "paper_1412_6862_amd", "tuned_shapes.json")
 
 
 def algorithmic_bytes_per_codeword(r: int) -> float:
@@ -39,8 +40,12 @@ def algorithmic_bytes_per_codeword(r: int) -> float:
 
 
 def kernel_source_digest() -> str:
+    """Digest of the kernel sources and the launch shapes the bench loads."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1412_6862_amd", "csrc", "*"))):
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1412_6862_amd", "csrc", "*")))
+    if os.path.exists(TUNED_SHAPES):
+        files.append(TUNED_SHAPES)
+    for p in files:
         with open(p, "rb") as fh:
             h.update(os.path.basename(p).encode())
             h.update(fh.read())
@@ -267,6 +272,52 @@ def serving_leg(dev, plain_gBps_per_r: dict, loads, n_requests: int, warm: int):
                         "pool 4 GiB", "points": out}
 
 
+def latency_leg(dev, reps: int):
+    """Hamming(7,4), one packet of 65,536 codewords (p = 0.5): a latency-bound
+    launch; p50/p99 of single-launch time over `reps` launches."""
+    import numpy as np
+    import torch
+
+    import paper_1412_6862_amd as hm
+
+    r, n = 3, 65536
+    cw = make_packet(r, n, 0.5, dev)
+    data = torch.empty(hm.hamming_data_bytes(n, r), dtype=torch.uint8, device=dev)
+    ep = torch.empty(n, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    t = time_events(lambda: hm.hamming_decode(cw, n, r, data, ep, stream), stream, 20, reps)
+    t = np.array(t) * 1e3
+    return {"workload": "Hamming(7,4), one packet of 65,536 codewords, 50% single-bit errors",
+            "launches": reps, "p50_us": round(float(np.percentile(t, 50)), 2),
+            "p99_us": round(float(np.percentile(t, 99)), 2),
+            "payload_Gbps_at_p50": round(n * 4 / float(np.percentile(t, 50)) / 1e3, 1)}
+
+
+def hamming127_leg(dev, reps: int):
+    """Hamming(127,120), 2^25 codewords, 70% clean / 25% one flip / 5% two
+    flips (the two-flip words are miscorrected by the deterministic rule)."""
+    import numpy as np
+    import torch
+
+    import paper_1412_6862_amd as hm
+    import synth
+
+    r, n = 7, 1 << 25
+    seed = synth.workload_seed("bench-r7", r)
+    cw = hm.encode(synth.message_stream_torch(seed, n, r, dev), n, r)
+    p1, p2 = synth.error_positions(seed, n, r, p_single=0.25, p_double=0.05)
+    cw ^= torch.from_numpy(synth.flip_masks(p1, p2, r).view(np.int64)).to(dev)
+    data = torch.empty(hm.hamming_data_bytes(n, r), dtype=torch.uint8, device=dev)
+    ep = torch.empty(n, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    t = time_events(lambda: hm.hamming_decode(cw, n, r, data, ep, stream), stream, 5, reps)
+    med = t[len(t) // 2]
+    algo = algorithmic_bytes_per_codeword(r) * n
+    return {"workload": "Hamming(127,120), 2^25 codewords, 70% clean / 25% one flip / 5% two flips",
+            "us_p50": round(med * 1e3, 2), "payload_Gbps": round(n * 120 / med / 1e6, 1),
+            "frac_hbm": round(algo / med / 1e6 / HBM_PEAK_GBPS, 4)}
+
+
 def cpu_baseline(log2_sample: int):
     """The oracle on the host cores over a slice of the same workload."""
     import oracle
@@ -305,10 +356,12 @@ def main() -> int:
     ap.add_argument("--cpu-log2", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--batch-packets", type=int, default=20000)
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
-    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-requests", type=int, default=100000)
-    ap.add_argument("--no-tune", action="store_true", help="keep the built-in launch shapes")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the autotuner before timing instead of loading the committed shapes")
+    ap.add_argument("--legs", default="latency,r7,batch,serve",
+                    help="extra legs after the plain one (which gives the reported value): "
+                         "comma-separated subset of latency,r7,batch,serve, or none")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (counter calibration)")
     args = ap.parse_args()
@@ -331,8 +384,14 @@ def main() -> int:
         print(json.dumps({"copy_bytes": src.numel() * 8, "launches": 5}), flush=True)
         return 0
     hm.library()
-    if not args.no_tune:
+    legs = set(args.legs.split(","))
+    if args.tune:
         hm.hamming_tune(None, 3)
+    elif os.path.exists(TUNED_SHAPES):
+        try:
+            hm.hamming_tune_load(TUNED_SHAPES)
+        except hm.HammingError:
+            pass    # shapes tuned on another device model: keep the built-in ones
     tuned = {"plain": {r: list(hm.hamming_plain_config_get(r)) for r in range(3, 8)},
              "batch": list(hm.hamming_batch_config_get())}
     n_cw = 1 << args.log2_cw
@@ -426,9 +485,13 @@ def main() -> int:
     }
     del packets
     torch.cuda.empty_cache()
-    if not args.no_batch:
+    if "latency" in legs:
+        out["latency_hamming74"] = latency_leg(dev, 1000)
+    if "r7" in legs:
+        out["hamming127"] = hamming127_leg(dev, 20)
+    if "batch" in legs:
         out["batched"] = batched_leg(dev, args.batch_packets, 5)
-    if not args.no_serve:
+    if "serve" in legs:
         gBps = {x["r"]: x["algorithmic_GBps"] for x in per_r}
         gBps.setdefault(7, gBps[DOMINANT_R])
         out["serving"] = serving_leg(dev, gBps, (0.1, 0.3, 0.5, 0.7, 0.9), args.serve_requests,

@@ -113,6 +113,28 @@ def message_stream(seed: int, n_cw: int, r: int) -> np.ndarray:
     return out
 
 
+def message_stream_slice(seed: int, first_cw: int, n_cw: int, r: int) -> np.ndarray:
+    """The message bits of codewords [first_cw, first_cw + n_cw) of the stream
+    ``message_stream(seed, ., r)`` describes, realigned to start at bit 0 and
+    with the bits after n_cw*k cleared (a slice of the same random stream)."""
+    _, k, _ = code_sizes(r)
+    b0 = first_cw * k
+    b1 = b0 + n_cw * k
+    w0, w1 = b0 // 64, (b1 + 63) // 64
+    a = np.concatenate([draws(seed, w0, w1 - w0), np.zeros(1, dtype=np.uint64)])
+    sh = np.uint64(b0 % 64)
+    if sh:
+        out = (a[:-1] >> sh) | (a[1:] << np.uint64(64 - int(sh)))
+    else:
+        out = a[:-1].copy()
+    nwords = (n_cw * k + 63) // 64
+    out = out[:nwords]
+    tail = (n_cw * k) % 64
+    if nwords and tail:
+        out[-1] &= np.uint64((1 << tail) - 1)
+    return out
+
+
 def _threshold(prob: float) -> int:
     """Integer threshold t such that a 53-bit uniform u is below t with
     probability ``prob`` (exact for prob = 0 and prob = 1)."""
@@ -131,7 +153,7 @@ def _second_position(u: np.ndarray, first: np.ndarray, n: int) -> np.ndarray:
 
 
 def error_positions(seed: int, n_cw: int, r: int, p_single: float = 0.0,
-                    p_double: float = 0.0) -> tuple[np.ndarray, np.ndarray]:
+                    p_double: float = 0.0, start: int = 0) -> tuple[np.ndarray, np.ndarray]:
     """Per-codeword channel errors.
 
     Each codeword independently gets one flipped bit with probability
@@ -139,6 +161,8 @@ def error_positions(seed: int, n_cw: int, r: int, p_single: float = 0.0,
     none otherwise.  Positions are uniform over all n positions (parity
     positions included); the two positions of a double error are a uniform
     unordered pair.  Returns (pos1, pos2) uint8 arrays, 0 meaning "no flip".
+    Codeword i uses draw ``start + i`` of the streams, so a slice of a longer
+    packet can be regenerated on its own.
     """
     n, _, _ = code_sizes(r)
     t1 = _threshold(p_single)
@@ -149,11 +173,11 @@ def error_positions(seed: int, n_cw: int, r: int, p_single: float = 0.0,
     pos2 = np.zeros(n_cw, dtype=np.uint8)
 
     def fill(a, b):
-        u = draws(s_kind, a, b - a) >> np.uint64(11)
+        u = draws(s_kind, start + a, b - a) >> np.uint64(11)
         one = u < np.uint64(t1)
         if t2 == 0:
             return
-        v = draws(s_pos, a, b - a)
+        v = draws(s_pos, start + a, b - a)
         first = _first_position(v, n)
         pos1[a:b] = np.where(u < np.uint64(t2), first, 0).astype(np.uint8)
         if t2 > t1:

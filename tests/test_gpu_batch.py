@@ -236,3 +236,58 @@ def test_batch_small_grid_hint_and_coarse_map(gpu_device):
         bd.decode(max_codewords=hint)
         torch.cuda.synchronize()
         _check_outputs(bd, descs, expect)
+
+
+def test_batch_full_size_workload_sampled_packets(gpu_device):
+    """The bench's batched workload at full size (20,000 packets, ~2.2e9
+    codewords) in the bench's launch configuration; sampled packets are
+    regenerated on the CPU from the same seeded streams, encoded and decoded
+    by the oracle, and compared with the batch output byte for byte."""
+    import os
+    import sys
+
+    import torch
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+
+    n_packets = 20000
+    seed = synth.workload_seed("bench-batch", 0)
+    arena, descs, per_r, n_cw, r = bench.build_batch(gpu_device, n_packets, seed)
+    del per_r
+    torch.cuda.empty_cache()
+    if os.path.exists(bench.TUNED_SHAPES):
+        try:
+            hm.hamming_tune_load(bench.TUNED_SHAPES)
+        except hm.HammingError:
+            pass
+    bd = hm.BatchDecoder(arena, n_packets)
+    bd.set_packets(descs)
+    bd.decode()
+    torch.cuda.synchronize()
+    assert not bd.status[:n_packets].cpu().numpy().any()
+    _, _, p = synth.batch_packets(seed, n_packets)
+    # position of each packet inside its r's concatenated stream
+    pos = np.zeros(n_packets, dtype=np.int64)
+    for rr in range(3, 8):
+        idx = np.flatnonzero(r == rr)
+        pos[idx] = np.concatenate([[0], np.cumsum(n_cw[idx])[:-1]])
+    rng = np.random.default_rng(3)
+    sample = set(rng.choice(n_packets, size=80, replace=False).tolist())
+    for rr in range(3, 8):
+        idx = np.flatnonzero(r == rr)
+        sample.add(int(idx[np.argmax(n_cw[idx])]))
+        sample.add(int(idx[np.argmin(n_cw[idx])]))
+    for i in sorted(sample):
+        rr, n = int(r[i]), int(n_cw[i])
+        sr = synth.subseed(seed, "r", rr)
+        msg = synth.message_stream_slice(sr, int(pos[i]), n, rr)
+        cw = oracle.encode(msg, n, rr)
+        p1, p2 = synth.error_positions(sr, n, rr, p_single=float(p[i]), start=int(pos[i]))
+        d_ref, e_ref = oracle.decode(cw ^ synth.flip_masks(p1, p2, rr), rr)
+        o = int(descs[i]["data_word_off"]) * 8
+        e = int(descs[i]["errpos_off"])
+        d_gpu = bd.data.view(torch.uint8)[o:o + d_ref.size].cpu().numpy()
+        e_gpu = bd.errpos[e:e + n].cpu().numpy()
+        assert np.array_equal(d_gpu, d_ref), "packet %d (r=%d, n=%d)" % (i, rr, n)
+        assert np.array_equal(e_gpu, e_ref), "packet %d (r=%d, n=%d)" % (i, rr, n)

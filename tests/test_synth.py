@@ -100,3 +100,18 @@ def test_torch_generator_matches_numpy_bit_for_bit():
         rates = torch.full((5000,), 0.3, dtype=torch.float64)
         m3 = synth.flip_masks_torch(4, 5000, r, rates, torch.device("cpu")).numpy().view(np.uint64)
         assert np.array_equal(m1, m3)
+
+
+@pytest.mark.parametrize("r", [3, 5, 7])
+def test_slices_regenerate_the_same_stream(r):
+    _, k, _ = synth.code_sizes(r)
+    full = synth.message_stream(31, 1000, r)
+    bits = np.unpackbits(full.view(np.uint8), bitorder="little")
+    for first, n in ((0, 1000), (1, 5), (17, 300), (999, 1), (64, 64)):
+        sl = synth.message_stream_slice(31, first, n, r)
+        sb = np.unpackbits(sl.view(np.uint8), bitorder="little")
+        assert np.array_equal(sb[:n * k], bits[first * k:(first + n) * k])
+        assert not sb[n * k:].any()
+    p1, p2 = synth.error_positions(8, 1000, r, p_single=0.3, p_double=0.1)
+    q1, q2 = synth.error_positions(8, 200, r, p_single=0.3, p_double=0.1, start=400)
+    assert np.array_equal(p1[400:600], q1) and np.array_equal(p2[400:600], q2)
