@@ -170,8 +170,12 @@ __device__ __forceinline__ void finish_tile(TileIn<R, U>& tin, uint64_t n_cw, ui
     auto& in = tin.in;
 
     // ---- transpose coalesced vectors to lane-contiguous codewords ----------
+    // Vector j is kept in LDS slot j ^ ((j / NV) % NV): the low bits are
+    // rotated per block of NV vectors, so the lane-strided reads below hit
+    // different banks while the lane-consecutive writes stay conflict free.
     if (tin.coalesced) {
         u32x4* lv = reinterpret_cast<u32x4*>(lds);
+        constexpr uint32_t NV = T::NV;
 #pragma unroll
         for (int v = 0; v < T::NV; ++v) {
             u32x4 x;
@@ -179,12 +183,14 @@ __device__ __forceinline__ void finish_tile(TileIn<R, U>& tin, uint64_t n_cw, ui
             x.y = in[4 * v + 1];
             x.z = in[4 * v + 2];
             x.w = in[4 * v + 3];
-            lv[64 * v + lane] = x;
+            const uint32_t j = 64u * v + lane;
+            lv[j ^ ((j / NV) % NV)] = x;
         }
         wave_sync();
 #pragma unroll
         for (int v = 0; v < T::NV; ++v) {
-            const u32x4 x = lv[lane * T::NV + v];
+            const uint32_t j = lane * NV + v;
+            const u32x4 x = lv[j ^ ((j / NV) % NV)];
             in[4 * v + 0] = x.x;
             in[4 * v + 1] = x.y;
             in[4 * v + 2] = x.z;
