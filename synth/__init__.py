@@ -300,9 +300,67 @@ def flip_masks_torch(seed: int, n_cw: int, r: int, p_single, device):
     return masks.reshape(-1)
 
 
+# --- segmented packets ------------------------------------------------------
+
+def packet_bytes(seed: int, n_packets: int, msg_bytes: int) -> np.ndarray:
+    """[n_packets, msg_bytes] uniformly random message bytes; packet q is
+    drawn from counters [q * W, (q + 1) * W), W = ceil(msg_bytes / 8)."""
+    w = (msg_bytes + 7) // 8
+    out = np.empty(n_packets * w, dtype=np.uint64)
+
+    def fill(a, b):
+        out[a:b] = draws(subseed(seed, "bytes"), a, b - a)
+
+    _chunked(n_packets * w, fill)
+    return out.view(np.uint8).reshape(n_packets, w * 8)[:, :msg_bytes].copy()
+
+
+def segment_flips(seed: int, n_packets: int, seg_start, seg_len, p_single: float,
+                  p_double: float = 0.0) -> tuple[np.ndarray, np.ndarray]:
+    """Channel errors of packets made of bit ranges: in every packet, each
+    range [seg_start[i], seg_start[i] + seg_len[i]) independently gets no
+    flip, one flip (probability p_single) or two distinct flips (p_double) at
+    uniform positions in the range.  Returns (bit1, bit2), int64 arrays of
+    shape [n_packets, len(seg_start)] holding the flipped bit indices within
+    the packet, -1 for none.  Range i of packet q uses counter q*T + i."""
+    start = np.asarray(seg_start, dtype=np.int64)
+    length = np.asarray(seg_len, dtype=np.int64)
+    T = start.size
+    total = n_packets * T
+    t1 = _threshold(p_single)
+    t2 = _threshold(min(1.0, p_single + p_double))
+    u = draws(subseed(seed, "seg-kind"), 0, total).reshape(n_packets, T) >> np.uint64(11)
+    v = draws(subseed(seed, "seg-pos"), 0, total).reshape(n_packets, T)
+    n = np.broadcast_to(length.astype(np.uint64), (n_packets, T))
+    first = np.uint64(1) + (((v >> np.uint64(32)) * n) >> np.uint64(32))
+    step = np.uint64(1) + (((v & np.uint64(0xFFFFFFFF)) * np.maximum(n - np.uint64(1), np.uint64(1)))
+                           >> np.uint64(32))
+    second = np.uint64(1) + ((first - np.uint64(1) + step) % n)
+    hit = u < np.uint64(t2)
+    two = (u >= np.uint64(t1)) & hit & (n > np.uint64(1))
+    bit1 = np.where(hit, first.astype(np.int64) - 1 + start, -1)
+    bit2 = np.where(two, second.astype(np.int64) - 1 + start, -1)
+    return bit1, bit2
+
+
+def apply_bit_flips(rows: np.ndarray, *bits: np.ndarray) -> None:
+    """XOR the given bit indices (LSB-first within each row, -1 = none) into
+    a [P, row_bytes] uint8 array in place."""
+    P, row = rows.shape
+    flat = rows.reshape(-1)
+    for b in bits:
+        q, _ = np.nonzero(b >= 0)
+        idx = b[b >= 0]
+        np.bitwise_xor.at(flat, q * row + idx // 8, (1 << (idx % 8)).astype(np.uint8))
+
+
 # --- workload recipes ------------------------------------------------------
 
 PLAIN_ERROR_RATES = (0.0, 0.01, 0.1, 0.5, 1.0)
+
+
+PAPER_PACKET_BYTES = (400, 800, 1200, 1600, 2000)
+PAPER_SEGMENTS = (2, 3, 4, 5, 6)
 
 
 def workload_seed(tag: str, r: int, extra: int | str = 0) -> int:

@@ -115,3 +115,21 @@ def test_slices_regenerate_the_same_stream(r):
     p1, p2 = synth.error_positions(8, 1000, r, p_single=0.3, p_double=0.1)
     q1, q2 = synth.error_positions(8, 200, r, p_single=0.3, p_double=0.1, start=400)
     assert np.array_equal(p1[400:600], q1) and np.array_equal(p2[400:600], q2)
+
+
+def test_segmented_packet_generators():
+    b = synth.packet_bytes(3, 1000, 13)
+    assert b.shape == (1000, 13) and abs(b.mean() - 127.5) < 2
+    assert np.array_equal(synth.packet_bytes(3, 10, 13), b[:10])
+    starts, lens = [0, 11, 22], [11, 11, 5]
+    b1, b2 = synth.segment_flips(5, 100000, starts, lens, 0.3, 0.1)
+    assert abs((b1 >= 0).mean() - 0.4) < 0.01 and abs((b2 >= 0).mean() - 0.1) < 0.005
+    for i, (a, n) in enumerate(zip(starts, lens)):
+        hit = b1[:, i][b1[:, i] >= 0]
+        assert hit.min() == a and hit.max() == a + n - 1
+        both = b2[:, i] >= 0
+        assert (b2[both, i] != b1[both, i]).all()
+        assert (b2[both, i] >= a).all() and (b2[both, i] < a + n).all()
+    rows = np.zeros((2, 4), dtype=np.uint8)
+    synth.apply_bit_flips(rows, np.array([[0, 9], [31, -1]]), np.array([[1, -1], [-1, -1]]))
+    assert rows.tolist() == [[3, 2, 0, 0], [0, 0, 0, 128]]
