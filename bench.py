@@ -318,6 +318,54 @@ def hamming127_leg(dev, reps: int):
             "frac_hbm": round(algo / med / 1e6 / HBM_PEAK_GBPS, 4)}
 
 
+def host_leg(dev, reps: int):
+    """Host-resident Hamming(63,57) packet of 2^26 codewords in pinned memory,
+    decoded through the copy pipeline: synchronous transfers (copy in,
+    decode, copy out, chunk after chunk) against the asynchronous schedule
+    over 3 streams, with the speedup Eq. 1 predicts from the measured
+    synchronous stage times.  PCIe-inclusive; never the reported value."""
+    import time
+
+    import numpy as np
+    import torch
+
+    import paper_1412_6862_amd as hm
+
+    r, n, chunk, streams = 6, 1 << 26, 1 << 22, 3
+    k = hm.hamming_message_bits(r)
+    cw = make_packet(r, n, P_SINGLE, dev).cpu().pin_memory()
+    data = torch.empty(hm.hamming_data_bytes(n, r), dtype=torch.uint8, pin_memory=True)
+    ep = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    wsb = hm.hamming_host_workspace_bytes(chunk, r, streams)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    n_chunks = n // chunk
+
+    def run(mode, times=False):
+        t0 = time.perf_counter()
+        st = hm.hamming_decode_host(cw, n, r, data, ep, chunk, mode, streams, ws, wsb, times=times)
+        return time.perf_counter() - t0, st
+
+    run(hm.HAMMING_TRANSFER_SYNC)
+    run(hm.HAMMING_TRANSFER_ASYNC)
+    sync = [run(hm.HAMMING_TRANSFER_SYNC, True) for _ in range(reps)]
+    asyn = [run(hm.HAMMING_TRANSFER_ASYNC)[0] for _ in range(reps)]
+    t_sync = float(np.median([s[0] for s in sync]))
+    t_async = float(np.median(asyn))
+    ps, dke, pr = (float(np.median([s[1][i] for s in sync])) / n_chunks for i in range(3))
+    eq1 = n_chunks * (ps + dke + pr) / (ps + n_chunks * dke + pr)
+    stage = max(ps, dke, pr)
+    pipe = n_chunks * (ps + dke + pr) / (ps + dke + pr + (n_chunks - 1) * stage)
+    return {"workload": "Hamming(63,57), 2^26 codewords (512 MiB) in pinned host memory, %d chunks of 2^22 "
+                        "codewords, %d streams, 10%% single-bit errors" % (n_chunks, streams),
+            "sync_ms": round(t_sync * 1e3, 2), "async_ms": round(t_async * 1e3, 2),
+            "async_speedup": round(t_sync / t_async, 3),
+            "chunk_ms": {"h2d": round(ps, 3), "decode": round(dke, 4), "d2h": round(pr, 3)},
+            "h2d_GBps": round(chunk * 8 / ps / 1e6, 1),
+            "d2h_GBps": round((chunk * (k + 8) / 8) / pr / 1e6, 1),
+            "eq1_predicted_speedup": round(eq1, 3), "stage_bound_speedup": round(pipe, 3),
+            "payload_Gbps_async": round(n * k / t_async / 1e9, 1)}
+
+
 def cpu_baseline(log2_sample: int):
     """The oracle on the host cores over a slice of the same workload."""
     import oracle
@@ -359,9 +407,9 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=100000)
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner before timing instead of loading the committed shapes")
-    ap.add_argument("--legs", default="latency,r7,batch,serve",
+    ap.add_argument("--legs", default="latency,r7,batch,serve,host",
                     help="extra legs after the plain one (which gives the reported value): "
-                         "comma-separated subset of latency,r7,batch,serve, or none")
+                         "comma-separated subset of latency,r7,batch,serve,host, or none")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (counter calibration)")
     args = ap.parse_args()
@@ -496,6 +544,8 @@ def main() -> int:
         gBps.setdefault(7, gBps[DOMINANT_R])
         out["serving"] = serving_leg(dev, gBps, (0.1, 0.3, 0.5, 0.7, 0.9), args.serve_requests,
                                      max(200, args.serve_requests // 10))
+    if "host" in legs:
+        out["host_pipeline"] = host_leg(dev, 3)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_log2)
     print(json.dumps(out), flush=True)

@@ -85,7 +85,13 @@ _SIGNATURES.update({
                               ctypes.POINTER(_u64)], _i32),
     "hamming_server_run_trace": ([_vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _u64, _vp, ctypes.POINTER(_u64)],
                                  _i32),
+    "hamming_host_workspace_bytes": ([_u64, _i32, ctypes.c_uint32], _u64),
+    "hamming_decode_host": ([_vp, _u64, _i32, _vp, _vp, _u64, _i32, ctypes.c_uint32, _vp, _u64,
+                             ctypes.POINTER(ctypes.c_double)], _i32),
 })
+
+HAMMING_TRANSFER_SYNC = 0
+HAMMING_TRANSFER_ASYNC = 1
 
 HAMMING_NO_ERRPOS = (1 << 64) - 1
 HAMMING_MAX_BATCH = 1 << 24
@@ -223,6 +229,21 @@ def hamming_batch_config_get() -> tuple[int, int, int, int]:
     return s.value, rt.value, b.value, g.value
 
 
+def hamming_host_workspace_bytes(chunk_cw: int, r: int, streams: int) -> int:
+    return int(library().hamming_host_workspace_bytes(chunk_cw, r, streams))
+
+
+def hamming_decode_host(host_cw, n_cw: int, r: int, host_data_out, host_errpos_out, chunk_cw: int, mode: int,
+                        streams: int, workspace, workspace_bytes: int, times: bool = False):
+    """Decode a host-resident packet through the copy pipeline; returns the
+    summed (h2d, decode, d2h) milliseconds when ``times`` is set."""
+    t = (ctypes.c_double * 3)() if times else None
+    _check(library().hamming_decode_host(_ptr(host_cw), n_cw, r, _ptr(host_data_out), _ptr(host_errpos_out),
+                                         chunk_cw, mode, streams, _ptr(workspace), workspace_bytes, t),
+           "hamming_decode_host")
+    return tuple(t) if times else None
+
+
 # ---- conveniences over torch tensors --------------------------------------------
 
 def words_per_codeword(r: int) -> int:
@@ -262,6 +283,27 @@ def encode(messages, n_cw: int, r: int, stream=None):
     out = torch.empty(n_cw * words_per_codeword(r), dtype=torch.int64, device=messages.device)
     hamming_encode(messages.contiguous(), n_cw, r, out, stream)
     return out
+
+
+def decode_host(codewords, r: int, chunk_cw: int = 1 << 22, mode: int = HAMMING_TRANSFER_ASYNC,
+                streams: int = 3, errpos: bool = True, device=None):
+    """Decode a host tensor of codewords (pin it for overlapping copies);
+    returns host (data, errpos) tensors, pinned when the input is."""
+    import torch
+
+    if codewords.device.type != "cpu":
+        raise ValueError("codewords must be a host tensor")
+    cw = codewords.contiguous().view(-1)
+    n_cw = cw.numel() // words_per_codeword(r)
+    pin = cw.is_pinned()
+    data = torch.empty(hamming_data_bytes(n_cw, r), dtype=torch.uint8, pin_memory=pin)
+    ep = torch.empty(n_cw, dtype=torch.uint8, pin_memory=pin) if errpos else None
+    wsb = hamming_host_workspace_bytes(chunk_cw, r, streams)
+    if wsb == 0:
+        raise HammingError(HAMMING_EINVAL, "hamming_host_workspace_bytes")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=device or torch.device("cuda"))
+    hamming_decode_host(cw, n_cw, r, data, ep, chunk_cw, mode, streams, ws, wsb)
+    return data, ep
 
 
 class BatchDecoder:

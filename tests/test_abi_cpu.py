@@ -179,3 +179,42 @@ def test_server_create_validation_codes():
     n = ctypes.c_uint32()
     assert lib.hamming_server_poll(None, None, 0, ctypes.byref(n)) == hm.HAMMING_EINVAL
     assert hm.hamming_server_now_ns() > 0
+
+
+def test_host_pipeline_workspace_and_validation_codes():
+    lib = hm.library()
+    for r in range(3, 8):
+        wpc = 2 if r == 7 else 1
+        one = hm.hamming_host_workspace_bytes(1 << 16, r, 1)
+        assert one >= (1 << 16) * 8 * wpc + hm.hamming_data_bytes(1 << 16, r) + (1 << 16)
+        assert one % 256 == 0
+        assert hm.hamming_host_workspace_bytes(1 << 16, r, 3) == 3 * one
+    assert hm.hamming_host_workspace_bytes(100, 4, 1) == 0          # not a multiple of 64
+    assert hm.hamming_host_workspace_bytes(0, 4, 1) == 0
+    assert hm.hamming_host_workspace_bytes(64, 8, 1) == 0
+    assert hm.hamming_host_workspace_bytes(64, 4, 0) == 0
+    assert hm.hamming_host_workspace_bytes(64, 4, 9) == 0
+
+    A = 1 << 20   # aligned fake addresses; never dereferenced
+    ws = hm.hamming_host_workspace_bytes(64, 4, 2)
+    call = lambda **kw: lib.hamming_decode_host(
+        kw.get("cw", A), kw.get("n", 1000), kw.get("r", 4), kw.get("data", A), kw.get("ep", A),
+        kw.get("chunk", 64), kw.get("mode", hm.HAMMING_TRANSFER_ASYNC), kw.get("streams", 2), kw.get("ws", A),
+        kw.get("wsb", ws), None)
+    assert call(r=2) == hm.HAMMING_EINVAL
+    assert call(mode=2) == hm.HAMMING_EINVAL
+    assert call(chunk=65) == hm.HAMMING_EINVAL
+    assert call(chunk=0) == hm.HAMMING_EINVAL
+    assert call(streams=0) == hm.HAMMING_EINVAL
+    assert call(streams=9) == hm.HAMMING_EINVAL
+    assert call(n=hm.HAMMING_MAX_CODEWORDS + 1) == hm.HAMMING_ERANGE
+    assert call(cw=0) == hm.HAMMING_EINVAL
+    assert call(data=0) == hm.HAMMING_EINVAL
+    assert call(ws=0) == hm.HAMMING_EINVAL
+    assert call(cw=A + 4) == hm.HAMMING_EALIGN
+    assert call(data=A + 1) == hm.HAMMING_EALIGN
+    assert call(ws=A + 128) == hm.HAMMING_EALIGN
+    assert call(wsb=ws - 1) == hm.HAMMING_ENOMEM
+    # the synchronous mode stages one chunk at a time, so one stream's share suffices
+    assert call(wsb=ws // 2 - 1, mode=hm.HAMMING_TRANSFER_SYNC) == hm.HAMMING_ENOMEM
+    assert call(n=0, cw=0, data=0, ws=0) == hm.HAMMING_OK
