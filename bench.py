@@ -13,7 +13,6 @@ from __future__ import annotations
 
 import argparse
 import hashlib
-import glob
 import json
 import os
 import sys
@@ -39,10 +38,15 @@ def algorithmic_bytes_per_codeword(r: int) -> float:
     return 8.0 * wpc + k / 8.0 + 1.0
 
 
+# sources the plain decode kernel and its launch configuration are built from
+DOMINANT_SOURCES = ("abi.hip", "decode_plain.hip", "hamming_device.h", "launch.h", "tile.h")
+
+
 def kernel_source_digest() -> str:
-    """Digest of the kernel sources and the launch shapes the bench loads."""
+    """Digest of the plain decode kernel's sources and the launch shapes the
+    bench loads."""
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1412_6862_amd", "csrc", "*")))
+    files = [os.path.join(ROOT, "paper_1412_6862_amd", "csrc", f) for f in DOMINANT_SOURCES]
     if os.path.exists(TUNED_SHAPES):
         files.append(TUNED_SHAPES)
     for p in files:
@@ -366,6 +370,118 @@ def host_leg(dev, reps: int):
             "payload_Gbps_async": round(n * k / t_async / 1e9, 1)}
 
 
+def planes_leg(dev, reps: int):
+    """Bit-plane input layout against the natural layout on the same received
+    words: 2^26 codewords (2^25 for r = 7), 10% single-bit errors."""
+    import torch
+
+    import paper_1412_6862_amd as hm
+
+    stream = torch.cuda.current_stream()
+    rows = []
+    for r in (3, 4, 5, 6, 7):
+        n = 1 << (25 if r == 7 else 26)
+        k = hm.hamming_message_bits(r)
+        cw = make_packet(r, n, P_SINGLE, dev)
+        planes, pw = hm.to_planes(cw, r)
+        data = torch.empty(hm.hamming_data_bytes(n, r), dtype=torch.uint8, device=dev)
+        ep = torch.empty(n, dtype=torch.uint8, device=dev)
+        t_nat = time_events(lambda: hm.hamming_decode(cw, n, r, data, ep, stream), stream, 3, reps)
+        t_pl = time_events(lambda: hm.hamming_decode_planes(planes, pw, n, r, data, ep, stream), stream, 3, reps)
+        nat, pl = t_nat[len(t_nat) // 2], t_pl[len(t_pl) // 2]
+        algo = n * (((1 << r) - 1) / 8.0 + k / 8.0 + 1.0)
+        rows.append({"r": r, "n_cw": n, "natural_us": round(nat * 1e3, 1), "planes_us": round(pl * 1e3, 1),
+                     "speedup": round(nat / pl, 3), "planes_Gcw_per_s": round(n / pl / 1e6, 1),
+                     "planes_bytes_per_cw": round(algo / n, 3), "planes_GBps": round(algo / pl / 1e6, 1),
+                     "planes_frac_hbm": round(algo / pl / 1e6 / HBM_PEAK_GBPS, 4)})
+        del cw, planes, data, ep
+        torch.cuda.empty_cache()
+    return {"workload": "same received words in the natural layout and in the bit-plane layout; "
+                        "2^26 codewords (2^25 for r = 7), 10% single-bit errors", "rows": rows}
+
+
+SEG_SHAPES = [(m, t) for m in (400, 800, 1200, 1600, 2000) for t in (2, 3, 4, 5, 6)]
+SEG_P_SINGLE, SEG_P_DOUBLE = 0.3, 0.05
+
+
+def segmented_algorithmic_bytes(msg_bytes: int, t: int) -> float:
+    """Encoded packet read + descriptor read + message write + syndromes + status."""
+    import paper_1412_6862_amd as hm
+
+    _, _, bits = hm.hamming_seg_layout(msg_bytes, t)
+    return bits / 8.0 + 32 + msg_bytes + 2 * t + 1
+
+
+def segmented_leg(dev, n_packets: int, reps: int, lat_reps: int):
+    """The paper's packets (Sec. II, Table 1 grid): M bytes in t shortened
+    segments.  Per shape: a batch of n_packets packets (encoded on the GPU,
+    flips from the seeded channel) decoded in one launch, and the latency of
+    a one-packet launch."""
+    import numpy as np
+    import torch
+
+    import paper_1412_6862_amd as hm
+    import synth
+
+    stream = torch.cuda.current_stream()
+    rows = []
+    for mb, t in SEG_SHAPES:
+        b = hm.SegmentedBatch(n_packets, mb, t, device=dev)
+        seed = synth.workload_seed("bench-seg", mb, t)
+        b.msg.copy_(synth.draws_torch(seed, 0, n_packets * b.msg_stride, dev))
+        b.encode()
+        k, r, _ = hm.hamming_seg_layout(mb, t)
+        n = np.asarray(k) + np.asarray(r)
+        starts = np.concatenate([[0], np.cumsum(n)[:-1]])
+        b1, b2 = synth.segment_flips(seed, n_packets, starts, n, SEG_P_SINGLE, SEG_P_DOUBLE)
+        base = (np.arange(n_packets, dtype=np.int64) * b.enc_stride * 64)[:, None]
+        bits = torch.from_numpy(np.concatenate([(b1 + base)[b1 >= 0], (b2 + base)[b2 >= 0]])).to(dev)
+        one = torch.ones_like(bits)
+        b.enc ^= torch.zeros_like(b.enc).scatter_add_(0, bits // 64, torch.bitwise_left_shift(one, bits % 64))
+        del bits, one
+        t_batch = time_events(lambda: b.decode(stream), stream, 3, reps)
+        med = t_batch[len(t_batch) // 2]
+        algo = segmented_algorithmic_bytes(mb, t) * n_packets
+        lat = np.array(time_events(lambda: hm.hamming_decode_segmented(
+            b.enc, b.enc.numel(), b.descs, 1, mb, b.msg, b.msg.numel(), b.syndromes, b.syndromes.numel(),
+            b.status, stream), stream, 20, lat_reps)) * 1e3
+        st = torch.bincount(b.status.to(torch.int64), minlength=3)[:3].cpu().tolist()
+        rows.append({"M": mb, "t": t, "batch_us": round(med * 1e3, 1),
+                     "packets_per_s": round(n_packets / med * 1e3, 0),
+                     "us_per_packet_batched": round(med * 1e3 / n_packets, 5),
+                     "GBps": round(algo / med / 1e6, 1), "frac_hbm": round(algo / med / 1e6 / HBM_PEAK_GBPS, 4),
+                     "single_packet_p50_us": round(float(np.percentile(lat, 50)), 2),
+                     "single_packet_p99_us": round(float(np.percentile(lat, 99)), 2),
+                     "status_clean_corrected_uncorrectable": st})
+        del b
+        torch.cuda.empty_cache()
+    return {"workload": "the paper's packets: M in {400..2000} bytes split into t in {2..6} shortened Hamming "
+                        "segments; %d packets per batch, per segment %.0f%% one flip / %.0f%% two flips"
+                        % (n_packets, SEG_P_SINGLE * 100, SEG_P_DOUBLE * 100), "shapes": rows}
+
+
+def cpu_segmented(n_packets: int):
+    """The oracle, one thread, per packet of each segmented shape."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    out = {}
+    for mb, t in SEG_SHAPES:
+        seed = synth.workload_seed("bench-seg-cpu", mb, t)
+        msgs = synth.packet_bytes(seed, n_packets, mb)
+        enc = oracle.seg_encode_many(msgs, t)
+        _, _, n, _ = oracle.seg_layout(mb, t)
+        starts = np.concatenate([[0], np.cumsum(n)[:-1]])
+        b1, b2 = synth.segment_flips(seed, n_packets, starts, n, SEG_P_SINGLE, SEG_P_DOUBLE)
+        synth.apply_bit_flips(enc, b1, b2)
+        t0 = time.perf_counter()
+        oracle.seg_decode_many(enc, mb, t, nthreads=1)
+        out["%d/%d" % (mb, t)] = round((time.perf_counter() - t0) / n_packets * 1e6, 2)
+    return out
+
+
 def cpu_baseline(log2_sample: int):
     """The oracle on the host cores over a slice of the same workload."""
     import oracle
@@ -392,6 +508,7 @@ def cpu_baseline(log2_sample: int):
         "kind": "oracle",
         "sample": "2^%d codewords of each of r=4,5,6 (p=%.2f), %d threads, decode only, %.2f s"
                   % (log2_sample, P_SINGLE, threads, elapsed),
+        "segmented_us_per_packet_1thread": cpu_segmented(100),
     }
 
 
@@ -407,9 +524,10 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=100000)
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner before timing instead of loading the committed shapes")
-    ap.add_argument("--legs", default="latency,r7,batch,serve,host",
+    ap.add_argument("--seg-packets", type=int, default=1 << 19)
+    ap.add_argument("--legs", default="latency,r7,batch,serve,host,seg,planes",
                     help="extra legs after the plain one (which gives the reported value): "
-                         "comma-separated subset of latency,r7,batch,serve,host, or none")
+                         "comma-separated subset of latency,r7,batch,serve,host,seg,planes, or none")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (counter calibration)")
     args = ap.parse_args()
@@ -546,8 +664,19 @@ def main() -> int:
                                      max(200, args.serve_requests // 10))
     if "host" in legs:
         out["host_pipeline"] = host_leg(dev, 3)
+    if "planes" in legs:
+        out["planes"] = planes_leg(dev, 10)
+    if "seg" in legs:
+        out["segmented"] = segmented_leg(dev, args.seg_packets, 5, 200)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_log2)
+        if "segmented" in out:
+            cpu = out["cpu_baseline"]["segmented_us_per_packet_1thread"]
+            for row in out["segmented"]["shapes"]:
+                c = cpu["%d/%d" % (row["M"], row["t"])]
+                row["speedup_vs_oracle_1thread"] = {
+                    "single_packet": round(c / row["single_packet_p50_us"], 1),
+                    "batched": round(c / row["us_per_packet_batched"], 0)}
     print(json.dumps(out), flush=True)
     return 0
 

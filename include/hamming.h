@@ -220,6 +220,155 @@ int hamming_decode_batch(const uint64_t *cw_arena, uint64_t cw_words,
 int hamming_batch_config_set(int schedule, uint32_t xcd_chunk, uint32_t grid_cap_blocks, int use_graph);
 int hamming_batch_config_get(int *schedule, uint32_t *xcd_chunk, uint32_t *grid_cap_blocks, int *use_graph);
 
+/* ---- bit-plane input layout -------------------------------------------------
+ *
+ * The index-set clustering of Sec. III.A (Fig. 4) carried to single
+ * positions, as a device format: plane p-1 (p = 1..n) holds position p of
+ * every codeword, codeword i at bit i%64 of 64-bit word i/64 of the plane;
+ * planes are plane_words words apart (plane_words >= ceil(n_cw/64)).  A
+ * codeword takes n bits of input instead of 64 (r <= 6) or 128 (r = 7).
+ * Bits of the last plane word past n_cw are ignored.  The decode's outputs are
+ * those of hamming_decode: dense message stream and errpos bytes.
+ */
+
+/* Words of a plane-layout packet with plane_words = ceil(n_cw/64); 0 for bad
+ * arguments. */
+uint64_t hamming_planes_words(uint64_t n_cw, int r);
+
+/*
+ * Decode n_cw codewords given in the plane layout.
+ *   planes     : device, n planes of plane_words 64-bit words (8-byte aligned).
+ *   data_out   : device, hamming_data_bytes(n_cw, r) bytes (8-byte aligned;
+ *                16-byte alignment enables vector stores).
+ *   errpos_out : device, n_cw bytes, or NULL.
+ * Returns HAMMING_OK, HAMMING_EINVAL, HAMMING_EALIGN, HAMMING_ERANGE (n_cw
+ * too large, or plane_words below ceil(n_cw/64)) or HAMMING_EDEVICE.
+ */
+int hamming_decode_planes(const uint64_t *planes, uint64_t plane_words, uint64_t n_cw, int r, void *data_out,
+                          uint8_t *errpos_out, hipStream_t stream);
+
+/* Convert n_cw codewords from the storage layout of hamming_decode into the
+ * plane layout (device buffers, 8-byte aligned; padding bits dropped; plane
+ * words past ceil(n_cw/32) 32-bit words are not written).  Same status codes
+ * as hamming_decode_planes. */
+int hamming_to_planes(const uint64_t *codewords, uint64_t n_cw, int r, uint64_t *planes, uint64_t plane_words,
+                      hipStream_t stream);
+
+/* ---- segmented packets ------------------------------------------------------
+ *
+ * The paper's own packet format (Sec. II, Fig. 1; shortened segments as in
+ * the worked example of Sec. III.A): a packet of M message bytes is split into
+ * t segments; segment i carries k_i = floor(8M/t) message bits, plus one for
+ * the first (8M mod t) segments, message bits [K_i, K_i + k_i) of the packet.
+ * It is a shortened Hamming codeword of n_i = k_i + r_i positions, r_i the
+ * smallest r >= 2 with 2^r - 1 - r >= k_i: checksum bits at positions 2^j,
+ * message bits at the other positions in ascending order.  The encoded packet
+ * is the dense LSB-first bit string of segment 1, then segment 2, ...:
+ * position p of segment i is bit o_i + p - 1, o_i = n_0 + ... + n_{i-1}, of a
+ * little-endian sequence of 64-bit words.  Bits after the last segment up to
+ * the end of its last word are ignored on input and written 0 by the encoder.
+ *
+ * Decoding a segment: s = syndrome (XOR over its index sets).  s = 0: clean;
+ * 1 <= s <= n_i: bit s is flipped; s > n_i: no single flip explains the
+ * checksum, the segment is detected-uncorrectable and passed on as received
+ * (a shortened code is not perfect, so this case exists).  The merged message
+ * is M bytes, message bit b of the packet being bit b%8 of byte b/8, written
+ * as ceil(M/8) whole 64-bit words whose bytes past M are 0.
+ */
+#define HAMMING_SEG_MAX_T 32          /* segments per packet */
+#define HAMMING_SEG_MAX_K 65519       /* message bits per segment (r_i <= 16) */
+#define HAMMING_SEG_MAX_BYTES 4096    /* message bytes per packet */
+#define HAMMING_SEG_INVALID 0xFF      /* status of a descriptor the call rejected */
+
+typedef struct hamming_seg_packet {
+    uint64_t enc_word_off;  /* first 64-bit word of the encoded packet in the encoded arena */
+    uint64_t msg_word_off;  /* first 64-bit word of the message in the message arena */
+    uint32_t msg_bytes;     /* M, 1..max_msg_bytes */
+    uint32_t t;             /* segments, 1..HAMMING_SEG_MAX_T, at most 8M */
+    uint64_t seg_off;       /* first entry of this packet's segments in the syndrome array */
+} hamming_seg_packet;       /* 32 bytes */
+
+/* Host helper: segment layout of a packet (k_out, r_out: t entries each, or
+ * NULL).  Returns the encoded length in bits, or -1 for a shape the decoder
+ * does not take (t outside [1, 32], 8M < t, M > HAMMING_SEG_MAX_BYTES or a
+ * segment above HAMMING_SEG_MAX_K message bits). */
+int64_t hamming_seg_layout(uint32_t msg_bytes, uint32_t t, uint32_t *k_out, uint32_t *r_out);
+
+/*
+ * Decode n_packets segmented packets, one wave per packet.
+ *   enc_arena, enc_words : device, the encoded packets (8-byte aligned).
+ *   descs               : device, n_packets descriptors (8-byte aligned).
+ *   max_msg_bytes       : an upper bound of every packet's msg_bytes,
+ *                         1..HAMMING_SEG_MAX_BYTES (sizes the LDS of a launch).
+ *   msg_arena, msg_words: device, receives the merged messages.
+ *   syndromes           : device, syndrome_count entries, or NULL; packet q's
+ *                         segment i writes entry seg_off + i with its s.
+ *   status              : device, n_packets bytes, or NULL: 0 clean, 1 some
+ *                         segment corrected, 2 some segment
+ *                         detected-uncorrectable, HAMMING_SEG_INVALID for a
+ *                         descriptor with a bad shape or a range outside its
+ *                         arena (nothing else is written for that packet).
+ * Packets must not overlap in the output arenas.  Returns HAMMING_OK,
+ * HAMMING_EINVAL, HAMMING_EALIGN, HAMMING_ERANGE (n_packets above
+ * HAMMING_MAX_BATCH) or HAMMING_EDEVICE.
+ */
+int hamming_decode_segmented(const uint64_t *enc_arena, uint64_t enc_words, const hamming_seg_packet *descs,
+                             uint32_t n_packets, uint32_t max_msg_bytes, uint64_t *msg_arena, uint64_t msg_words,
+                             uint16_t *syndromes, uint64_t syndrome_count, uint8_t *status, hipStream_t stream);
+
+/*
+ * Encode n_packets messages into segmented packets (the transmitter half):
+ * reads ceil(M/8) words at msg_word_off (bytes past M ignored), writes the
+ * encoded words at enc_word_off.  A descriptor with a bad shape or a range
+ * outside its arena is skipped.  Same argument rules and status codes as
+ * hamming_decode_segmented.
+ */
+int hamming_encode_segmented(const uint64_t *msg_arena, uint64_t msg_words, const hamming_seg_packet *descs,
+                             uint32_t n_packets, uint32_t max_msg_bytes, uint64_t *enc_arena, uint64_t enc_words,
+                             hipStream_t stream);
+
+/* ---- host-resident packets: transfer pipeline ------------------------------ */
+
+/* Transfer scheduling of hamming_decode_host (Sec. III.B): one chunk after
+ * another on one stream, or chunks spread over several streams so that
+ * host-to-device copies, decodes and device-to-host copies of different chunks
+ * overlap. */
+enum hamming_transfer_mode { HAMMING_TRANSFER_SYNC = 0, HAMMING_TRANSFER_ASYNC = 1 };
+
+/* Device workspace bytes hamming_decode_host needs for chunks of chunk_cw
+ * codewords of code r on `streams` streams; 0 for invalid arguments. */
+uint64_t hamming_host_workspace_bytes(uint64_t chunk_cw, int r, uint32_t streams);
+
+/*
+ * Decode a packet that lives in host memory: the packet is cut into chunks of
+ * chunk_cw codewords (a multiple of 64, so every chunk's messages start on a
+ * 64-bit word of the output stream); each chunk is copied to the device,
+ * decoded with hamming_decode's kernels and copied back into host_data_out /
+ * host_errpos_out.  Results are identical to hamming_decode on the whole
+ * packet.  Returns after every copy has finished (the call synchronises its
+ * streams).
+ *   host_cw         : host, n_cw words (2*n_cw for r = 7).  For copies to
+ *                     overlap with kernels the three host buffers should be
+ *                     pinned (hipHostMalloc); pageable memory works but copies
+ *                     then serialise.
+ *   host_data_out   : host, hamming_data_bytes(n_cw, r) bytes.
+ *   host_errpos_out : host, n_cw bytes, or NULL.
+ *   mode            : HAMMING_TRANSFER_SYNC or HAMMING_TRANSFER_ASYNC.
+ *   streams         : streams used by the asynchronous mode (1..8); the
+ *                     synchronous mode uses one.
+ *   workspace       : device, hamming_host_workspace_bytes(chunk_cw, r,
+ *                     streams) bytes, 256-byte aligned, owned by the caller.
+ *   times_ms        : NULL, or double[3] receiving the summed milliseconds of
+ *                     host-to-device copies, decodes and device-to-host copies
+ *                     (per-operation events; meaningful in the synchronous
+ *                     mode, where the operations do not overlap).
+ * Returns HAMMING_OK, HAMMING_EINVAL, HAMMING_EALIGN, HAMMING_ERANGE,
+ * HAMMING_ENOMEM (workspace too small) or HAMMING_EDEVICE.
+ */
+int hamming_decode_host(const uint64_t *host_cw, uint64_t n_cw, int r, void *host_data_out,
+                        uint8_t *host_errpos_out, uint64_t chunk_cw, int mode, uint32_t streams,
+                        void *workspace, uint64_t workspace_bytes, double *times_ms);
+
 /* ---- autotuning ------------------------------------------------------------ */
 
 /*

@@ -90,6 +90,25 @@ _SIGNATURES.update({
                              ctypes.POINTER(ctypes.c_double)], _i32),
 })
 
+_SIGNATURES.update({
+    "hamming_seg_layout": ([ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
+                            ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int64),
+    "hamming_decode_segmented": ([_vp, _u64, _vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _u64, _vp, _u64, _vp,
+                                  _vp], _i32),
+    "hamming_encode_segmented": ([_vp, _u64, _vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _u64, _vp], _i32),
+})
+
+_SIGNATURES.update({
+    "hamming_planes_words": ([_u64, _i32], _u64),
+    "hamming_decode_planes": ([_vp, _u64, _u64, _i32, _vp, _vp, _vp], _i32),
+    "hamming_to_planes": ([_vp, _u64, _i32, _vp, _u64, _vp], _i32),
+})
+
+HAMMING_SEG_MAX_T = 32
+HAMMING_SEG_MAX_K = 65519
+HAMMING_SEG_MAX_BYTES = 4096
+HAMMING_SEG_INVALID = 0xFF
+
 HAMMING_TRANSFER_SYNC = 0
 HAMMING_TRANSFER_ASYNC = 1
 
@@ -229,6 +248,78 @@ def hamming_batch_config_get() -> tuple[int, int, int, int]:
     return s.value, rt.value, b.value, g.value
 
 
+def hamming_planes_words(n_cw: int, r: int) -> int:
+    return int(library().hamming_planes_words(n_cw, r))
+
+
+def hamming_decode_planes(planes, plane_words: int, n_cw: int, r: int, data_out, errpos_out=None,
+                          stream=None) -> None:
+    _check(library().hamming_decode_planes(_ptr(planes), plane_words, n_cw, r, _ptr(data_out), _ptr(errpos_out),
+                                           _stream(stream)), "hamming_decode_planes")
+
+
+def hamming_to_planes(codewords, n_cw: int, r: int, planes, plane_words: int, stream=None) -> None:
+    _check(library().hamming_to_planes(_ptr(codewords), n_cw, r, _ptr(planes), plane_words, _stream(stream)),
+           "hamming_to_planes")
+
+
+def to_planes(codewords, r: int, stream=None):
+    """Plane layout of a device tensor of codewords; returns (planes tensor,
+    plane_words)."""
+    import torch
+
+    cw = codewords.contiguous().view(-1)
+    n_cw = cw.numel() // words_per_codeword(r)
+    pw = (n_cw + 63) // 64
+    planes = torch.zeros(((1 << r) - 1) * pw, dtype=torch.int64, device=cw.device)
+    hamming_to_planes(cw, n_cw, r, planes, pw, stream)
+    return planes, pw
+
+
+def decode_planes(planes, plane_words: int, n_cw: int, r: int, errpos: bool = True, stream=None):
+    """Decode a device tensor in the plane layout; returns (data, errpos)."""
+    import torch
+
+    data = torch.empty(hamming_data_bytes(n_cw, r), dtype=torch.uint8, device=planes.device)
+    ep = torch.empty(n_cw, dtype=torch.uint8, device=planes.device) if errpos else None
+    hamming_decode_planes(planes, plane_words, n_cw, r, data, ep, stream)
+    return data, ep
+
+
+def seg_packet_dtype():
+    """numpy dtype of ``hamming_seg_packet`` (32 bytes, the C struct's layout)."""
+    import numpy as np
+
+    return np.dtype([("enc_word_off", "<u8"), ("msg_word_off", "<u8"), ("msg_bytes", "<u4"), ("t", "<u4"),
+                     ("seg_off", "<u8")])
+
+
+def hamming_seg_layout(msg_bytes: int, t: int):
+    """(k, r, encoded_bits) of a segmented packet; raises for a shape the
+    decoder does not take."""
+    k = (ctypes.c_uint32 * max(t, 1))()
+    r = (ctypes.c_uint32 * max(t, 1))()
+    tot = library().hamming_seg_layout(msg_bytes, t, k, r) if 1 <= t <= HAMMING_SEG_MAX_T else -1
+    if tot < 0:
+        raise HammingError(HAMMING_EINVAL, "hamming_seg_layout")
+    return list(k)[:t], list(r)[:t], int(tot)
+
+
+def hamming_decode_segmented(enc_arena, enc_words: int, descs, n_packets: int, max_msg_bytes: int, msg_arena,
+                             msg_words: int, syndromes=None, syndrome_count: int = 0, status=None,
+                             stream=None) -> None:
+    _check(library().hamming_decode_segmented(_ptr(enc_arena), enc_words, _ptr(descs), n_packets, max_msg_bytes,
+                                              _ptr(msg_arena), msg_words, _ptr(syndromes), syndrome_count,
+                                              _ptr(status), _stream(stream)), "hamming_decode_segmented")
+
+
+def hamming_encode_segmented(msg_arena, msg_words: int, descs, n_packets: int, max_msg_bytes: int, enc_arena,
+                             enc_words: int, stream=None) -> None:
+    _check(library().hamming_encode_segmented(_ptr(msg_arena), msg_words, _ptr(descs), n_packets, max_msg_bytes,
+                                              _ptr(enc_arena), enc_words, _stream(stream)),
+           "hamming_encode_segmented")
+
+
 def hamming_host_workspace_bytes(chunk_cw: int, r: int, streams: int) -> int:
     return int(library().hamming_host_workspace_bytes(chunk_cw, r, streams))
 
@@ -304,6 +395,42 @@ def decode_host(codewords, r: int, chunk_cw: int = 1 << 22, mode: int = HAMMING_
     ws = torch.empty(wsb, dtype=torch.uint8, device=device or torch.device("cuda"))
     hamming_decode_host(cw, n_cw, r, data, ep, chunk_cw, mode, streams, ws, wsb)
     return data, ep
+
+
+class SegmentedBatch:
+    """Device arenas for ``n_packets`` segmented packets of one shape
+    (msg_bytes, t), packed back to back: encoded packet q at word
+    q * enc_stride, message q at word q * msg_stride, syndromes q*t..q*t+t-1."""
+
+    def __init__(self, n_packets: int, msg_bytes: int, t: int, device=None):
+        import numpy as np
+        import torch
+
+        dev = device or torch.device("cuda")
+        _, _, bits = hamming_seg_layout(msg_bytes, t)
+        self.n_packets, self.msg_bytes, self.t = n_packets, msg_bytes, t
+        self.enc_stride = (bits + 63) // 64
+        self.msg_stride = (msg_bytes + 7) // 8
+        d = np.zeros(n_packets, dtype=seg_packet_dtype())
+        q = np.arange(n_packets, dtype=np.uint64)
+        d["enc_word_off"] = q * np.uint64(self.enc_stride)
+        d["msg_word_off"] = q * np.uint64(self.msg_stride)
+        d["msg_bytes"] = msg_bytes
+        d["t"] = t
+        d["seg_off"] = q * np.uint64(t)
+        self.descs = torch.from_numpy(d.view(np.uint8)).to(dev)
+        self.enc = torch.zeros(n_packets * self.enc_stride, dtype=torch.int64, device=dev)
+        self.msg = torch.zeros(n_packets * self.msg_stride, dtype=torch.int64, device=dev)
+        self.syndromes = torch.zeros(n_packets * t, dtype=torch.int16, device=dev)
+        self.status = torch.zeros(n_packets, dtype=torch.uint8, device=dev)
+
+    def decode(self, stream=None) -> None:
+        hamming_decode_segmented(self.enc, self.enc.numel(), self.descs, self.n_packets, self.msg_bytes, self.msg,
+                                 self.msg.numel(), self.syndromes, self.syndromes.numel(), self.status, stream)
+
+    def encode(self, stream=None) -> None:
+        hamming_encode_segmented(self.msg, self.msg.numel(), self.descs, self.n_packets, self.msg_bytes, self.enc,
+                                 self.enc.numel(), stream)
 
 
 class BatchDecoder:

@@ -89,8 +89,11 @@ int hamming_tune(const char* cache_path, uint32_t flags, hipStream_t stream)
     if (!do_plain && !do_batch) return HAMMING_EINVAL;
     const uint64_t n6 = uint64_t(1) << 26;              // codewords per plain trial (2^25 for r = 7)
     DevBuf cw, data, ep, ws, descs_dev;
-    if (hipMalloc(&cw.p, n6 * 8) != hipSuccess || hipMalloc(&data.p, n6 * 8) != hipSuccess ||
-        hipMalloc(&ep.p, n6) != hipSuccess) {
+    hipError_t e = hipMalloc(&cw.p, n6 * 8);
+    if (e == hipSuccess) e = hipMalloc(&data.p, n6 * 8);
+    if (e == hipSuccess) e = hipMalloc(&ep.p, n6);
+    if (e != hipSuccess) {
+        fprintf(stderr, "hamming_tune: device allocation failed: %s\n", hipGetErrorString(e));
         (void)hipGetLastError();
         return HAMMING_ENOMEM;
     }
@@ -156,7 +159,10 @@ int hamming_tune(const char* cache_path, uint32_t flags, hipStream_t stream)
         if (rc != HAMMING_OK) return rc;
         if (off > n6 || dw > n6 || eb > n6) return HAMMING_ERANGE;
         const uint64_t wsb = hamming_batch_workspace_bytes(np);
-        if (hipMalloc(&ws.p, wsb) != hipSuccess || hipMalloc(&descs_dev.p, np * sizeof(hamming_packet) + 8) != hipSuccess) {
+        e = hipMalloc(&ws.p, wsb);
+        if (e == hipSuccess) e = hipMalloc(&descs_dev.p, np * sizeof(hamming_packet) + 8);
+        if (e != hipSuccess) {
+            fprintf(stderr, "hamming_tune: device allocation failed: %s\n", hipGetErrorString(e));
             (void)hipGetLastError();
             return HAMMING_ENOMEM;
         }

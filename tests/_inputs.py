@@ -30,3 +30,17 @@ def to_device(a: np.ndarray, device):
 
 def to_host_u8(t) -> np.ndarray:
     return t.cpu().numpy().view(np.uint8)
+
+
+def to_planes(words: np.ndarray, n_cw: int, r: int, plane_words: int | None = None) -> np.ndarray:
+    """Plane layout of received words (a pure re-arrangement of bits):
+    plane p-1 holds position p of every codeword, codeword i at bit i%64 of
+    word i/64.  Returns uint64 [n, plane_words]."""
+    n = (1 << r) - 1
+    wpc = 2 if r == 7 else 1
+    pw = plane_words or (n_cw + 63) // 64
+    w = np.ascontiguousarray(words, dtype=np.uint64).reshape(n_cw, wpc)
+    bits = np.unpackbits(w.view(np.uint8).reshape(n_cw, 8 * wpc), axis=1, bitorder="little")[:, :n]
+    planes = np.zeros((n, pw * 64), dtype=np.uint8)
+    planes[:, :n_cw] = bits.T
+    return np.packbits(planes, axis=1, bitorder="little").view(np.uint64)

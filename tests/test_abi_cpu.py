@@ -218,3 +218,66 @@ def test_host_pipeline_workspace_and_validation_codes():
     # the synchronous mode stages one chunk at a time, so one stream's share suffices
     assert call(wsb=ws // 2 - 1, mode=hm.HAMMING_TRANSFER_SYNC) == hm.HAMMING_ENOMEM
     assert call(n=0, cw=0, data=0, ws=0) == hm.HAMMING_OK
+
+
+def test_segmented_layout_matches_the_documented_rule():
+    import numpy as np
+
+    assert hm.seg_packet_dtype().itemsize == 32
+    k, r, bits = hm.hamming_seg_layout(7, 8)
+    assert k == [7] * 8 and r == [4] * 8 and bits == 88
+    for mb, t in ((400, 2), (2000, 6), (1, 3), (4096, 1), (4096, 32), (13, 5)):
+        k, r, bits = hm.hamming_seg_layout(mb, t)
+        assert sum(k) == 8 * mb and max(k) - min(k) <= 1 and k == sorted(k, reverse=True)
+        assert all((1 << ri) - 1 - ri >= ki and (ri == 2 or (1 << (ri - 1)) - ri < ki) for ki, ri in zip(k, r))
+        assert bits == sum(k) + sum(r)
+    for mb, t in ((0, 1), (1, 9), (10, 0), (10, 33), (4097, 2)):
+        with pytest.raises(hm.HammingError):
+            hm.hamming_seg_layout(mb, t)
+    assert np.dtype(hm.seg_packet_dtype()).names[:2] == ("enc_word_off", "msg_word_off")
+
+
+def test_segmented_validation_codes():
+    lib = hm.library()
+    A = 1 << 20
+    dec = lambda **kw: lib.hamming_decode_segmented(
+        kw.get("enc", A), 100, kw.get("descs", A), kw.get("n", 4), kw.get("mx", 2000), kw.get("msg", A), 100,
+        kw.get("syn", A), 10, None, None)
+    enc = lambda **kw: lib.hamming_encode_segmented(
+        kw.get("msg", A), 100, kw.get("descs", A), kw.get("n", 4), kw.get("mx", 2000), kw.get("enc", A), 100, None)
+    for call in (dec, enc):
+        assert call(mx=0) == hm.HAMMING_EINVAL
+        assert call(mx=hm.HAMMING_SEG_MAX_BYTES + 1) == hm.HAMMING_EINVAL
+        assert call(n=hm.HAMMING_MAX_BATCH + 1) == hm.HAMMING_ERANGE
+        assert call(enc=0) == hm.HAMMING_EINVAL
+        assert call(msg=0) == hm.HAMMING_EINVAL
+        assert call(descs=0) == hm.HAMMING_EINVAL
+        assert call(enc=A + 4) == hm.HAMMING_EALIGN
+        assert call(msg=A + 1) == hm.HAMMING_EALIGN
+        assert call(descs=A + 4) == hm.HAMMING_EALIGN
+        assert call(n=0, enc=0, msg=0, descs=0) == hm.HAMMING_OK
+    assert dec(syn=A + 1) == hm.HAMMING_EALIGN
+
+
+def test_planes_words_and_validation_codes():
+    lib = hm.library()
+    for r in range(3, 8):
+        n = (1 << r) - 1
+        assert hm.hamming_planes_words(1, r) == n
+        assert hm.hamming_planes_words(64, r) == n
+        assert hm.hamming_planes_words(65, r) == 2 * n
+        assert hm.hamming_planes_words(0, r) == 0
+    assert hm.hamming_planes_words(10, 8) == 0
+    A = 1 << 20
+    dec = lambda **kw: lib.hamming_decode_planes(kw.get("pl", A), kw.get("pw", 2), kw.get("n", 100),
+                                                 kw.get("r", 4), kw.get("d", A), kw.get("e", A), None)
+    conv = lambda **kw: lib.hamming_to_planes(kw.get("cw", A), kw.get("n", 100), kw.get("r", 4),
+                                              kw.get("pl", A), kw.get("pw", 2), None)
+    assert dec(r=2) == hm.HAMMING_EINVAL and conv(r=8) == hm.HAMMING_EINVAL
+    assert dec(pl=0) == hm.HAMMING_EINVAL and dec(d=0) == hm.HAMMING_EINVAL
+    assert conv(cw=0) == hm.HAMMING_EINVAL and conv(pl=0) == hm.HAMMING_EINVAL
+    assert dec(pw=1) == hm.HAMMING_ERANGE and conv(pw=1) == hm.HAMMING_ERANGE
+    assert dec(n=hm.HAMMING_MAX_CODEWORDS + 1) == hm.HAMMING_ERANGE
+    assert dec(pl=A + 4) == hm.HAMMING_EALIGN and dec(d=A + 4) == hm.HAMMING_EALIGN
+    assert conv(cw=A + 4) == hm.HAMMING_EALIGN and conv(pl=A + 2) == hm.HAMMING_EALIGN
+    assert dec(n=0, pl=0, d=0) == hm.HAMMING_OK and conv(n=0, cw=0, pl=0) == hm.HAMMING_OK
