@@ -56,9 +56,10 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic():
+def recorded_traffic(kernel: str):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter summary, if it was taken from the current kernel sources."""
+    counter summary, if it was taken from the current kernel sources and the
+    same kernel instance (lane width) that this run launches."""
     if not os.path.exists(PROFILE_GLOB):
         return None
     fields = {}
@@ -68,6 +69,8 @@ def recorded_traffic():
                 k, v = line[2:].split(":", 1)
                 fields[k.strip()] = v.strip().strip("`")
     if fields.get("kernel source digest") != kernel_source_digest():
+        return None
+    if fields.get("kernel", "").replace(" ", "").replace("hm::", "") != kernel:
         return None
     try:
         return float(fields["HBM bytes per launch (scaled)"])
@@ -246,7 +249,7 @@ def serving_leg(dev, plain_gBps_per_r: dict, loads, n_requests: int, warm: int):
     # bandwidth on its r; the offered load is rho over the mean of these
     nbytes = np.array([float(n) * algorithmic_bytes_per_codeword(int(x)) for n, x in zip(sizes, r)])
     t_plain = nbytes / np.array([plain_gBps_per_r[int(x)] for x in r]) / 1e9
-    srv = hm.Server(pool, slots=4, max_batch_packets=4096, max_batch_codewords=1 << 24,
+    srv = hm.Server(pool, slots=4, max_batch_packets=4096, max_batch_codewords=1 << 26,
                     output_pool_bytes=4 << 30, auto_release=True)
     out = []
     try:
@@ -612,7 +615,8 @@ def main() -> int:
             "payload_Gbps": round(n_cw * k / avg / 1e6, 1),
         })
     dom = next(x for x in per_r if x["r"] == DOMINANT_R)
-    traffic = recorded_traffic()
+    dominant_kernel = "decode_plain_kernel<6,%d>" % hm.hamming_plain_config_get(DOMINANT_R)[0]
+    traffic = recorded_traffic(dominant_kernel)
     bits_per_step = sum(n_cw * ((1 << r) - 1 - r) for r in WORKLOAD_R)
     value = bits_per_step / (ms_per_step * 1e-3) / 1e9
 
@@ -636,7 +640,7 @@ def main() -> int:
             "n_cw_per_packet": n_cw, "r": list(WORKLOAD_R), "p_single": P_SINGLE,
         },
         "roofline": {
-            "kernel": "decode_plain_kernel<6,%d>" % hm.hamming_plain_config_get(DOMINANT_R)[0],
+            "kernel": dominant_kernel,
             "bound": "hbm",
             "achieved": dom["algorithmic_GBps"],
             "peak": HBM_PEAK_GBPS,

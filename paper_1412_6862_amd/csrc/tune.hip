@@ -71,7 +71,9 @@ std::string device_name()
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
-    std::string s = std::string(prop.name) + " " + prop.gcnArchName;
+    // the architecture, not the marketing name: the latter depends on host
+    // tables that tools and containers do not always provide
+    std::string s = prop.gcnArchName;
     for (auto& c : s)
         if (c == '"' || c == '\\' || c == '\n') c = ' ';
     return s;
