@@ -41,6 +41,7 @@ struct BatchArgs {
     uint32_t* fine;
     uint32_t coarse_cap;
     uint32_t fine_cap;
+    uint32_t fine_blocks;   // grid of the fine-map kernel (it loops over entries beyond the grid)
 };
 
 inline uint32_t batch_coarse_capacity(uint32_t max_packets) { return 2 * max_packets + 1024; }

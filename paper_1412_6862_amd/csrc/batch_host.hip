@@ -179,6 +179,9 @@ int hamming_decode_batch(const uint64_t* cw_arena, uint64_t cw_words, const hamm
     if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
     if (blocks < 1) blocks = 1;
     const uint32_t grid = uint32_t(blocks);
+    // the fine map has at most one entry per tile of that bound
+    const uint64_t fine_entries = tiles < a.fine_cap ? tiles : a.fine_cap;
+    a.fine_blocks = uint32_t((fine_entries + 255) / 256);
 
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (stream && hipStreamIsCapturing(stream, &cs) != hipSuccess) return HAMMING_EDEVICE;

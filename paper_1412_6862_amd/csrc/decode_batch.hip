@@ -150,14 +150,16 @@ __global__ __launch_bounds__(256) void batch_coarse_kernel(BatchArgs a)
 
 __global__ __launch_bounds__(256) void batch_fine_kernel(BatchArgs a)
 {
-    const uint64_t j = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (j >= a.ws->n_fine) return;
-    const uint64_t t = j << a.ws->fine_log2;
-    const uint64_t jc = t >> a.ws->coarse_log2;
-    const uint32_t lo = a.coarse[jc];
-    // the packet holding tile t lies between the coarse entries around it
-    const uint32_t hi = (jc + 1 < a.ws->n_coarse) ? a.coarse[jc + 1] + 1 : uint32_t(a.ws->n_packets);
-    a.fine[j] = search_packet(a.tile_start, t, lo, hi);
+    const uint64_t n_fine = a.ws->n_fine;
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t j = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < n_fine; j += stride) {
+        const uint64_t t = j << a.ws->fine_log2;
+        const uint64_t jc = t >> a.ws->coarse_log2;
+        const uint32_t lo = a.coarse[jc];
+        // the packet holding tile t lies between the coarse entries around it
+        const uint32_t hi = (jc + 1 < a.ws->n_coarse) ? a.coarse[jc + 1] + 1 : uint32_t(a.ws->n_packets);
+        a.fine[j] = search_packet(a.tile_start, t, lo, hi);
+    }
 }
 
 // Last packet p in [0, n) with tile_start[p] <= t, given tile_start[lo] <= t
@@ -231,7 +233,7 @@ static hipError_t launch_batch_s(const BatchArgs& a, uint32_t grid, hipStream_t 
     hipLaunchKernelGGL(batch_coarse_kernel, dim3((a.coarse_cap + 255) / 256), dim3(256), 0, stream, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_fine_kernel, dim3((a.fine_cap + 255) / 256), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(batch_fine_kernel, dim3(a.fine_blocks), dim3(256), 0, stream, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((decode_batch_kernel<S>), dim3(grid), dim3(kBlockThreads), 0, stream, a, a.ws, a.fine,

@@ -157,12 +157,28 @@ __global__ __launch_bounds__(64 * PlaneShape<R>::WAVES) void decode_planes_kerne
             X[m] = 0;
         }
     }
+    if constexpr (K == 4) {
+        // Hamming(7,4): output dword w holds codewords 8w..8w+7, four bits
+        // each; spread byte w of message plane m to every fourth bit
 #pragma unroll
-    for (int b = 0; b < NB; ++b) transpose32(X + 32 * b);
+        for (int w = 0; w < 4; ++w) {
+            uint32_t out = 0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                uint32_t x = (X[m] >> (8 * w)) & 0xFFu;
+                x = (x | (x << 12)) & 0x000F000Fu;
+                x = (x | (x << 6)) & 0x03030303u;
+                x = (x | (x << 3)) & 0x11111111u;
+                out |= x << m;
+            }
+            Mw[lane * K + w] = out;
+        }
+    } else {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) transpose32(X + 32 * b);
 
-    // a6: codeword c's message bits [32b, 32b+32) are X[32b + c]; append
-    // them in stream order (c*K + 32b) and emit each completed dword
-    {
+        // a6: codeword c's message bits [32b, 32b+32) are X[32b + c]; append
+        // them in stream order (c*K + 32b) and emit each completed dword
         uint32_t acc = 0;
         int filled = 0, wout = 0;
 #pragma unroll

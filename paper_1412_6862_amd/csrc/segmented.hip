@@ -6,9 +6,12 @@
 // computed here one 64-position word at a time and reduced across the wave.
 //
 // One wave per packet: the encoded packet is staged in the wave's slice of
-// LDS, syndromes are reduced with cross-lane XORs, the corrections are LDS
-// atomics, and each lane then assembles whole 64-bit words of the merged
-// message from the runs of message positions between checksum positions.
+// LDS, the position words of all segments are dealt to the lanes and their
+// syndrome contributions XORed into per-segment LDS accumulators, the
+// corrections are LDS atomics, and each lane then assembles whole 64-bit words
+// of the merged message from the runs of message positions between checksum
+// positions.  Segment offsets are closed-form (message sizes take two
+// values), so no lookup table is read.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -19,9 +22,8 @@ using hm::wave_sync;
 
 namespace {
 
-constexpr uint32_t kSegWaves = 4;                      // packets per block
-constexpr uint32_t kTableU32 = 3 * (HAMMING_SEG_MAX_T + 1);
-constexpr uint32_t kTableWords = (kTableU32 + 1) / 2;  // per-wave segment table, in 64-bit words
+constexpr uint32_t kSegWaves = 4;                          // packets per block
+constexpr uint32_t kSynWords = HAMMING_SEG_MAX_T / 2;      // per-wave syndrome accumulators, in 64-bit words
 
 // Longest encoded packet of at most max_msg_bytes message bytes, in 64-bit
 // words, plus two zero words that unaligned two-word reads may touch.
@@ -50,88 +52,110 @@ __device__ __forceinline__ uint64_t read_bits64(const uint64_t* L, uint64_t bit)
     return sh ? (L[q] >> sh) | (L[q + 1] << (64 - sh)) : L[q];
 }
 
-__device__ __forceinline__ uint32_t wave_xor(uint32_t v)
+// Segment layout of one packet in closed form.  The first `rem` segments
+// carry q+1 message bits and nA positions, the others q bits and nB
+// positions, so every offset is a product and a min, and the segment that
+// holds a given bit is one division.  All fields are wave-uniform.
+struct Layout {
+    uint32_t t, q, rem, nA, nB, nwA, nwB, total;
+
+    __device__ uint32_t K(uint32_t i) const { return i * q + min(i, rem); }            // first message bit
+    __device__ uint32_t k(uint32_t i) const { return q + (i < rem ? 1u : 0u); }
+    __device__ uint32_t o(uint32_t i) const { return i * nB + min(i, rem) * (nA - nB); }  // first stream bit
+    __device__ uint32_t n(uint32_t i) const { return i < rem ? nA : nB; }
+    __device__ uint32_t seg_of_msg(uint32_t m) const
+    {
+        const uint32_t a = rem * (q + 1);
+        return m < a ? m / (q + 1) : rem + (m - a) / q;
+    }
+    __device__ uint32_t seg_of_bit(uint32_t b) const
+    {
+        const uint32_t a = rem * nA;
+        return b < a ? b / nA : rem + (b - a) / nB;
+    }
+    __device__ uint32_t syndrome_words() const { return rem * nwA + (t - rem) * nwB; }
+};
+
+// Validates the packet shape; returns false for one this launch cannot take.
+__device__ __forceinline__ bool make_layout(uint32_t msg_bytes, uint32_t t, uint32_t max_msg_bytes, Layout& L)
 {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v ^= __shfl_xor(v, d, 64);
+    if (t < 1 || t > HAMMING_SEG_MAX_T || msg_bytes < 1 || msg_bytes > max_msg_bytes || 8u * msg_bytes < t) return false;
+    const uint32_t bits = 8u * msg_bytes;
+    L.t = t;
+    L.q = bits / t;
+    L.rem = bits % t;
+    if (L.q + (L.rem ? 1u : 0u) > HAMMING_SEG_MAX_K) return false;
+    L.nA = L.q + 1 + seg_checksum_bits(L.q + 1);
+    L.nB = L.q + seg_checksum_bits(L.q);
+    L.nwA = L.nA / 64 + 1;
+    L.nwB = L.nB / 64 + 1;
+    L.total = L.o(t);
+    return true;
+}
+
+// Contribution of position word w of a segment (positions 64w..64w+63, bit
+// q of the word = position 64w + q) to its syndrome: the low six bits of a
+// position are those of q, the higher bits those of 64w (Algorithm 1's XOR
+// over index sets, 64 positions at a time).
+__device__ __forceinline__ uint32_t word_syndrome(const uint64_t* L, uint32_t o, uint32_t n, uint32_t w)
+{
+    uint64_t x = (o == 0 && w == 0) ? (L[0] << 1) : read_bits64(L, uint64_t(o) + 64u * w - 1u);
+    if (w == 0) x &= ~uint64_t(1);                     // there is no position 0
+    const uint32_t hi = n - 64u * w;                    // last valid bit index in this word
+    if (hi < 63) x &= (uint64_t(2) << hi) - 1;
+    uint32_t v = 0;
+    v |= uint32_t(__popcll(x & 0xAAAAAAAAAAAAAAAAull) & 1) << 0;
+    v |= uint32_t(__popcll(x & 0xCCCCCCCCCCCCCCCCull) & 1) << 1;
+    v |= uint32_t(__popcll(x & 0xF0F0F0F0F0F0F0F0ull) & 1) << 2;
+    v |= uint32_t(__popcll(x & 0xFF00FF00FF00FF00ull) & 1) << 3;
+    v |= uint32_t(__popcll(x & 0xFFFF0000FFFF0000ull) & 1) << 4;
+    v |= uint32_t(__popcll(x & 0xFFFFFFFF00000000ull) & 1) << 5;
+    if (__popcll(x) & 1) v |= 64u * w;
     return v;
 }
 
-// Per-wave segment table in LDS: K[i] (first message bit of segment i,
-// K[t] = 8M), o[i] (first stream bit, o[t] = encoded length), k[i].
-struct SegTable {
-    uint32_t* K;
-    uint32_t* o;
-    uint32_t* k;
-};
-
-// Validates the descriptor and fills the segment table; returns the encoded
-// length in bits, or 0 for a packet this launch cannot take (uniform).
-__device__ __forceinline__ uint32_t build_table(uint32_t msg_bytes, uint32_t t, uint32_t max_msg_bytes, uint32_t lane,
-                                                SegTable tab)
+// Syndromes of all segments: the position words of every segment form one
+// flat list dealt to the lanes; each lane XORs its words' contributions into
+// the segment's accumulator in LDS.  S must be zero and visible on entry;
+// the result is visible to the whole wave on return.
+__device__ __forceinline__ void all_syndromes(const uint64_t* L, const Layout& Lo, uint32_t* S, uint32_t lane)
 {
-    if (t < 1 || t > HAMMING_SEG_MAX_T || msg_bytes < 1 || msg_bytes > max_msg_bytes || 8u * msg_bytes < t) return 0;
-    const uint32_t bits = 8u * msg_bytes;
-    if ((bits + t - 1) / t > HAMMING_SEG_MAX_K) return 0;
-    uint32_t ki = 0, ni = 0;
-    if (lane < t) {
-        ki = bits / t + (lane < bits % t ? 1u : 0u);
-        ni = ki + seg_checksum_bits(ki);
-    }
-    uint32_t sk = ki, sn = ni;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t a = __shfl_up(sk, d, 64), b = __shfl_up(sn, d, 64);
-        if (lane >= uint32_t(d)) {
-            sk += a;
-            sn += b;
+    const uint32_t split = Lo.rem * Lo.nwA, words = Lo.syndrome_words();
+    for (uint32_t g = lane; g < words; g += 64) {
+        uint32_t i, w;
+        if (g < split) {
+            i = g / Lo.nwA;
+            w = g - i * Lo.nwA;
+        } else {
+            const uint32_t h = g - split;
+            i = h / Lo.nwB;
+            w = h - i * Lo.nwB;
+            i += Lo.rem;
         }
+        const uint32_t v = word_syndrome(L, Lo.o(i), Lo.n(i), w);
+        if (v) atomicXor(&S[i], v);
     }
-    if (lane < t) {
-        tab.K[lane] = sk - ki;
-        tab.o[lane] = sn - ni;
-        tab.k[lane] = ki;
-    }
-    if (lane == t - 1) {
-        tab.K[t] = sk;
-        tab.o[t] = sn;
-    }
-    return __shfl(sn, int(t - 1), 64);
+    wave_sync();
 }
 
-// Syndrome of segment i: positions 1..n of the segment are stream bits
-// o + p - 1.  Word w of the segment covers positions 64w..64w+63, so bit q
-// of the word is position 64w + q: its low six bits are q, its higher bits
-// are those of 64w.  Uniform result on every lane.
-__device__ __forceinline__ uint32_t segment_syndrome(const uint64_t* L, uint32_t o, uint32_t n, uint32_t lane)
+// The message positions below 64 (3, 5..7, 9..15, 17..31, 33..63) carry a
+// segment's first 57 message bits; given positions 1..64 as bits 0..63 of w,
+// this compacts them with constant masks and shifts.
+constexpr uint32_t kHeadBits = 57;
+
+__device__ __forceinline__ uint64_t head_message(uint64_t w)
 {
-    uint32_t s = 0;
-    const uint32_t nw = n / 64 + 1;
-    for (uint32_t w = lane; w < nw; w += 64) {
-        uint64_t x = (o == 0 && w == 0) ? (L[0] << 1) : read_bits64(L, uint64_t(o) + 64u * w - 1u);
-        if (w == 0) x &= ~uint64_t(1);                     // there is no position 0
-        const uint32_t hi = n - 64u * w;                    // last valid bit index in this word
-        if (hi < 63) x &= (uint64_t(2) << hi) - 1;
-        uint32_t v = 0;
-        v |= uint32_t(__popcll(x & 0xAAAAAAAAAAAAAAAAull) & 1) << 0;
-        v |= uint32_t(__popcll(x & 0xCCCCCCCCCCCCCCCCull) & 1) << 1;
-        v |= uint32_t(__popcll(x & 0xF0F0F0F0F0F0F0F0ull) & 1) << 2;
-        v |= uint32_t(__popcll(x & 0xFF00FF00FF00FF00ull) & 1) << 3;
-        v |= uint32_t(__popcll(x & 0xFFFF0000FFFF0000ull) & 1) << 4;
-        v |= uint32_t(__popcll(x & 0xFFFFFFFF00000000ull) & 1) << 5;
-        if (__popcll(x) & 1) v |= 64u * w;
-        s ^= v;
-    }
-    return wave_xor(s);
+    return ((w >> 2) & 0x1ull) | (((w >> 4) & 0x7ull) << 1) | (((w >> 8) & 0x7Full) << 4) |
+           (((w >> 16) & 0x7FFFull) << 11) | (((w >> 32) & 0x7FFFFFFFull) << 26);
 }
 
-// Run of message positions containing message bit mu of a segment: the
-// positions strictly between 2^j and 2^(j+1) carry message bits
-// mu = p - j - 2.  Returns j.
+// Run of message positions containing message bit mu >= 57 of a segment:
+// the positions strictly between 2^j and 2^(j+1) carry message bits
+// mu = p - j - 2.  Returns j (at least 6).
 __device__ __forceinline__ uint32_t run_of(uint32_t mu)
 {
     uint32_t j = 31u - __clz(mu + 2u);
-    if (j < 1) j = 1;
+    if (j < 6) j = 6;
     while ((2u << j) - j - 2u <= mu) ++j;
     return j;
 }
@@ -147,7 +171,7 @@ struct SegArgs {
     uint16_t* syndromes;
     uint64_t syndrome_count;
     uint8_t* status;
-    uint32_t slice_words;      // per-wave LDS slice (table excluded)
+    uint32_t slice_words;      // per-wave LDS slice (syndrome accumulators excluded)
 };
 
 __global__ __launch_bounds__(64 * kSegWaves) void seg_decode_kernel(SegArgs a)
@@ -157,15 +181,15 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_decode_kernel(SegArgs a)
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t pk = uint64_t(blockIdx.x) * kSegWaves + wib;
     if (pk >= a.n_packets) return;
-    uint64_t* L = lds + wib * (a.slice_words + kTableWords);
-    uint32_t* t32 = reinterpret_cast<uint32_t*>(L + a.slice_words);
-    const SegTable tab{t32, t32 + (HAMMING_SEG_MAX_T + 1), t32 + 2 * (HAMMING_SEG_MAX_T + 1)};
+    uint64_t* L = lds + wib * (a.slice_words + kSynWords);
+    uint32_t* S = reinterpret_cast<uint32_t*>(L + a.slice_words);
 
     const hamming_seg_packet d = a.descs[pk];
     const uint32_t M = d.msg_bytes, t = d.t;
-    const uint32_t total = build_table(M, t, a.max_msg_bytes, lane, tab);
-    const uint64_t ew = (uint64_t(total) + 63) / 64, mw = (uint64_t(M) + 7) / 8;
-    const bool ok = total != 0 && d.enc_word_off <= a.enc_words && ew <= a.enc_words - d.enc_word_off &&
+    Layout Lo;
+    const bool shape_ok = make_layout(M, t, a.max_msg_bytes, Lo);
+    const uint64_t ew = (uint64_t(Lo.total) + 63) / 64, mw = (uint64_t(M) + 7) / 8;
+    const bool ok = shape_ok && d.enc_word_off <= a.enc_words && ew <= a.enc_words - d.enc_word_off &&
                     d.msg_word_off <= a.msg_words && mw <= a.msg_words - d.msg_word_off &&
                     (!a.syndromes || (d.seg_off <= a.syndrome_count && t <= a.syndrome_count - d.seg_off));
     if (!ok) {
@@ -176,19 +200,15 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_decode_kernel(SegArgs a)
     const uint64_t* src = a.enc + d.enc_word_off;
     for (uint32_t w = lane; w < ew; w += 64) L[w] = __builtin_nontemporal_load(src + w);
     if (lane < 2) L[ew + lane] = 0;
+    if (lane < HAMMING_SEG_MAX_T) S[lane] = 0;
     wave_sync();
 
-    uint32_t my_s = 0;
-    for (uint32_t i = 0; i < t; ++i) {
-        const uint32_t o = tab.o[i];
-        const uint32_t s = segment_syndrome(L, o, tab.o[i + 1] - o, lane);
-        if (lane == i) my_s = s;
-    }
-    wave_sync();   // every lane has read the received bits before any correction
+    all_syndromes(L, Lo, S, lane);
+    const uint32_t my_s = lane < t ? S[lane] : 0u;
 
     uint32_t st = 0;
     if (lane < t) {
-        const uint32_t o = tab.o[lane], n = tab.o[lane + 1] - o;
+        const uint32_t o = Lo.o(lane), n = Lo.n(lane);
         if (my_s >= 1 && my_s <= n) {
             const uint32_t bit = o + my_s - 1;
             atomicXor(reinterpret_cast<unsigned long long*>(&L[bit >> 6]), 1ull << (bit & 63));
@@ -208,19 +228,29 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_decode_kernel(SegArgs a)
     for (uint32_t ow = lane; ow < mw; ow += 64) {
         uint32_t m = 64u * ow;
         const uint32_t end = min(m + 64u, nbits);
-        uint32_t i = 0;
-        while (i + 1 < t && tab.K[i + 1] <= m) ++i;
+        uint32_t i = Lo.seg_of_msg(m);
+        uint32_t K = Lo.K(i), k = Lo.k(i), R = Lo.o(i) - K;   // R: checksum bits before segment i
         uint64_t acc = 0;
         while (m < end) {
-            const uint32_t K = tab.K[i], k = tab.k[i];
             const uint32_t mu = m - K;
             if (mu >= k) {
                 ++i;
+                K += k;
+                k = Lo.k(i);
+                R = Lo.o(i) - K;
                 continue;
             }
-            const uint32_t j = run_of(mu);
-            const uint32_t len = min(min((2u << j) - j - 2u, k) - mu, end - m);
-            uint64_t v = read_bits64(L, uint64_t(m) + (tab.o[i] - K) + j + 1);
+            uint64_t v;
+            uint32_t lim;
+            if (mu < kHeadBits) {
+                v = head_message(read_bits64(L, uint64_t(K) + R)) >> mu;
+                lim = kHeadBits;
+            } else {
+                const uint32_t j = run_of(mu);
+                v = read_bits64(L, uint64_t(m) + R + j + 1);
+                lim = (2u << j) - j - 2u;
+            }
+            const uint32_t len = min(min(lim, k) - mu, end - m);
             if (len < 64) v &= (uint64_t(1) << len) - 1;
             acc |= v << (m - 64u * ow);
             m += len;
@@ -236,20 +266,17 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_encode_kernel(SegArgs a)
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t pk = uint64_t(blockIdx.x) * kSegWaves + wib;
     if (pk >= a.n_packets) return;
-    uint64_t* E = lds + wib * (a.slice_words + kTableWords);     // encoded words, then the message words
-    uint32_t* t32 = reinterpret_cast<uint32_t*>(E + a.slice_words);
-    const SegTable tab{t32, t32 + (HAMMING_SEG_MAX_T + 1), t32 + 2 * (HAMMING_SEG_MAX_T + 1)};
+    uint64_t* E = lds + wib * (a.slice_words + kSynWords);     // encoded words, then the message words
+    uint32_t* S = reinterpret_cast<uint32_t*>(E + a.slice_words);
 
     const hamming_seg_packet d = a.descs[pk];
     const uint32_t M = d.msg_bytes, t = d.t;
-    const uint32_t total = build_table(M, t, a.max_msg_bytes, lane, tab);
-    const uint64_t ew = (uint64_t(total) + 63) / 64, mw = (uint64_t(M) + 7) / 8;
-    const bool ok = total != 0 && d.enc_word_off <= a.enc_words && ew <= a.enc_words - d.enc_word_off &&
+    Layout Lo;
+    const bool shape_ok = make_layout(M, t, a.max_msg_bytes, Lo);
+    const uint64_t ew = (uint64_t(Lo.total) + 63) / 64, mw = (uint64_t(M) + 7) / 8;
+    const bool ok = shape_ok && d.enc_word_off <= a.enc_words && ew <= a.enc_words - d.enc_word_off &&
                     d.msg_word_off <= a.msg_words && mw <= a.msg_words - d.msg_word_off;
-    if (!ok) {
-        if (a.status && lane == 0) a.status[pk] = HAMMING_SEG_INVALID;
-        return;
-    }
+    if (!ok) return;
     uint64_t* Mw = E + enc_slice_words(a.max_msg_bytes);
     const uint64_t* src = a.msg + d.msg_word_off;
     for (uint32_t w = lane; w < mw; w += 64) Mw[w] = src[w];
@@ -257,17 +284,17 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_encode_kernel(SegArgs a)
         Mw[mw + lane] = 0;
         E[ew + lane] = 0;
     }
+    if (lane < HAMMING_SEG_MAX_T) S[lane] = 0;
     wave_sync();
 
     // message bits into their positions, checksum positions left 0
     for (uint32_t e = lane; e < ew; e += 64) {
         uint32_t b = 64u * e;
-        const uint32_t end = min(b + 64u, total);
-        uint32_t i = 0;
-        while (i + 1 < t && tab.o[i + 1] <= b) ++i;
+        const uint32_t end = min(b + 64u, Lo.total);
+        uint32_t i = Lo.seg_of_bit(b);
         uint64_t acc = 0;
         while (b < end) {
-            const uint32_t o = tab.o[i], n = tab.o[i + 1] - o;
+            const uint32_t o = Lo.o(i), n = Lo.n(i);
             const uint32_t p = b - o + 1;
             if (p > n) {
                 ++i;
@@ -280,7 +307,7 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_encode_kernel(SegArgs a)
             const uint32_t j = 31u - __clz(p);
             const uint32_t last = min((2u << j) - 1u, n);
             const uint32_t len = min(last - p + 1u, end - b);
-            uint64_t v = read_bits64(Mw, uint64_t(tab.K[i]) + p - j - 2u);
+            uint64_t v = read_bits64(Mw, uint64_t(Lo.K(i)) + p - j - 2u);
             if (len < 64) v &= (uint64_t(1) << len) - 1;
             acc |= v << (b - 64u * e);
             b += len;
@@ -290,22 +317,15 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_encode_kernel(SegArgs a)
     wave_sync();
 
     // checksum position 2^j takes bit j of the syndrome of the message bits alone
-    uint32_t my_s = 0;
-    for (uint32_t i = 0; i < t; ++i) {
-        const uint32_t o = tab.o[i];
-        const uint32_t s = segment_syndrome(E, o, tab.o[i + 1] - o, lane);
-        if (lane == i) my_s = s;
-    }
-    wave_sync();
+    all_syndromes(E, Lo, S, lane);
     if (lane < t) {
-        const uint32_t o = tab.o[lane];
-        for (uint32_t j = 0; my_s >> j; ++j) {
-            if (!((my_s >> j) & 1)) continue;
+        const uint32_t s = S[lane], o = Lo.o(lane);
+        for (uint32_t j = 0; s >> j; ++j) {
+            if (!((s >> j) & 1)) continue;
             const uint32_t bit = o + (1u << j) - 1u;
             atomicOr(reinterpret_cast<unsigned long long*>(&E[bit >> 6]), 1ull << (bit & 63));
         }
     }
-    if (a.status && lane == 0) a.status[pk] = 0;
     wave_sync();
     uint64_t* dst = const_cast<uint64_t*>(a.enc) + d.enc_word_off;
     for (uint32_t w = lane; w < ew; w += 64) __builtin_nontemporal_store(E[w], dst + w);
@@ -353,7 +373,7 @@ int hamming_decode_segmented(const uint64_t* enc_arena, uint64_t enc_words, cons
     if (syndromes && (reinterpret_cast<uintptr_t>(syndromes) & 1u)) return HAMMING_EALIGN;
     SegArgs a{enc_arena, enc_words, descs, n_packets, max_msg_bytes, msg_arena, msg_words,
               syndromes, syndromes ? syndrome_count : 0, status, enc_slice_words(max_msg_bytes)};
-    const size_t lds = size_t(kSegWaves) * (a.slice_words + kTableWords) * 8;
+    const size_t lds = size_t(kSegWaves) * (a.slice_words + kSynWords) * 8;
     const uint32_t blocks = (n_packets + kSegWaves - 1) / kSegWaves;
     hipLaunchKernelGGL(seg_decode_kernel, dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
     return hipGetLastError() == hipSuccess ? HAMMING_OK : HAMMING_EDEVICE;
@@ -367,7 +387,7 @@ int hamming_encode_segmented(const uint64_t* msg_arena, uint64_t msg_words, cons
     if (rc != HAMMING_OK || n_packets == 0) return rc;
     SegArgs a{enc_arena, enc_words, descs, n_packets, max_msg_bytes, const_cast<uint64_t*>(msg_arena), msg_words,
               nullptr, 0, nullptr, enc_slice_words(max_msg_bytes) + msg_slice_words(max_msg_bytes)};
-    const size_t lds = size_t(kSegWaves) * (a.slice_words + kTableWords) * 8;
+    const size_t lds = size_t(kSegWaves) * (a.slice_words + kSynWords) * 8;
     const uint32_t blocks = (n_packets + kSegWaves - 1) / kSegWaves;
     hipLaunchKernelGGL(seg_encode_kernel, dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
     return hipGetLastError() == hipSuccess ? HAMMING_OK : HAMMING_EDEVICE;

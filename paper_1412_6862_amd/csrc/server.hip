@@ -110,7 +110,7 @@ struct Slot {
 
 // Grid-size hints (codewords) below the largest batch: one graph per tier per
 // slot, so a small batch does not launch the grid of the largest one.
-constexpr uint64_t kTiers[] = {uint64_t(1) << 18, uint64_t(1) << 21};
+constexpr uint64_t kTiers[] = {uint64_t(1) << 18, uint64_t(1) << 21, uint64_t(1) << 24};
 
 }  // namespace
 
