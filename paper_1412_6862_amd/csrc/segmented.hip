@@ -96,44 +96,43 @@ __device__ __forceinline__ bool make_layout(uint32_t msg_bytes, uint32_t t, uint
 // Contribution of position word w of a segment (positions 64w..64w+63, bit
 // q of the word = position 64w + q) to its syndrome: the low six bits of a
 // position are those of q, the higher bits those of 64w (Algorithm 1's XOR
-// over index sets, 64 positions at a time).
+// over index sets, 64 positions at a time).  Bits q and q+32 share bits 0..4
+// of q, so those five parities are taken on the XOR of the two halves.
 __device__ __forceinline__ uint32_t word_syndrome(const uint64_t* L, uint32_t o, uint32_t n, uint32_t w)
 {
     uint64_t x = (o == 0 && w == 0) ? (L[0] << 1) : read_bits64(L, uint64_t(o) + 64u * w - 1u);
     if (w == 0) x &= ~uint64_t(1);                     // there is no position 0
     const uint32_t hi = n - 64u * w;                    // last valid bit index in this word
     if (hi < 63) x &= (uint64_t(2) << hi) - 1;
-    uint32_t v = 0;
-    v |= uint32_t(__popcll(x & 0xAAAAAAAAAAAAAAAAull) & 1) << 0;
-    v |= uint32_t(__popcll(x & 0xCCCCCCCCCCCCCCCCull) & 1) << 1;
-    v |= uint32_t(__popcll(x & 0xF0F0F0F0F0F0F0F0ull) & 1) << 2;
-    v |= uint32_t(__popcll(x & 0xFF00FF00FF00FF00ull) & 1) << 3;
-    v |= uint32_t(__popcll(x & 0xFFFF0000FFFF0000ull) & 1) << 4;
-    v |= uint32_t(__popcll(x & 0xFFFFFFFF00000000ull) & 1) << 5;
-    if (__popcll(x) & 1) v |= 64u * w;
+    const uint32_t h = uint32_t(x >> 32), f = uint32_t(x) ^ h;
+    uint32_t v = __popc(f & 0xAAAAAAAAu) & 1u;
+    v |= (__popc(f & 0xCCCCCCCCu) & 1u) << 1;
+    v |= (__popc(f & 0xF0F0F0F0u) & 1u) << 2;
+    v |= (__popc(f & 0xFF00FF00u) & 1u) << 3;
+    v |= (__popc(f & 0xFFFF0000u) & 1u) << 4;
+    v |= (__popc(h) & 1u) << 5;
+    if (__popc(f) & 1u) v |= 64u * w;
     return v;
 }
 
 // Syndromes of all segments: the position words of every segment form one
-// flat list dealt to the lanes; each lane XORs its words' contributions into
-// the segment's accumulator in LDS.  S must be zero and visible on entry;
-// the result is visible to the whole wave on return.
+// flat list dealt to the lanes (lane L takes words L, L+64, ...); each lane
+// walks its (segment, word) position forward and XORs its words'
+// contributions into the segment's accumulator in LDS.  S must be zero and
+// visible on entry; the result is visible to the whole wave on return.
 __device__ __forceinline__ void all_syndromes(const uint64_t* L, const Layout& Lo, uint32_t* S, uint32_t lane)
 {
-    const uint32_t split = Lo.rem * Lo.nwA, words = Lo.syndrome_words();
+    const uint32_t words = Lo.syndrome_words();
+    uint32_t i = 0, w = lane, nw = Lo.t > 0 && Lo.rem > 0 ? Lo.nwA : Lo.nwB;
     for (uint32_t g = lane; g < words; g += 64) {
-        uint32_t i, w;
-        if (g < split) {
-            i = g / Lo.nwA;
-            w = g - i * Lo.nwA;
-        } else {
-            const uint32_t h = g - split;
-            i = h / Lo.nwB;
-            w = h - i * Lo.nwB;
-            i += Lo.rem;
+        while (w >= nw) {          // move to the segment holding word g
+            w -= nw;
+            ++i;
+            nw = i < Lo.rem ? Lo.nwA : Lo.nwB;
         }
         const uint32_t v = word_syndrome(L, Lo.o(i), Lo.n(i), w);
         if (v) atomicXor(&S[i], v);
+        w += 64;
     }
     wave_sync();
 }
@@ -225,11 +224,11 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_decode_kernel(SegArgs a)
     // merge: lane-owned 64-bit words of the packet's message
     const uint32_t nbits = 8u * M;
     uint64_t* dst = a.msg + d.msg_word_off;
+    uint32_t i = Lo.seg_of_msg(64u * lane);
+    uint32_t K = Lo.K(i), k = Lo.k(i), R = Lo.o(i) - K;       // R: checksum bits before segment i
     for (uint32_t ow = lane; ow < mw; ow += 64) {
         uint32_t m = 64u * ow;
         const uint32_t end = min(m + 64u, nbits);
-        uint32_t i = Lo.seg_of_msg(m);
-        uint32_t K = Lo.K(i), k = Lo.k(i), R = Lo.o(i) - K;   // R: checksum bits before segment i
         uint64_t acc = 0;
         while (m < end) {
             const uint32_t mu = m - K;
