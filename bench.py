@@ -250,7 +250,7 @@ def serving_leg(dev, plain_gBps_per_r: dict, loads, n_requests: int, warm: int):
     nbytes = np.array([float(n) * algorithmic_bytes_per_codeword(int(x)) for n, x in zip(sizes, r)])
     t_plain = nbytes / np.array([plain_gBps_per_r[int(x)] for x in r]) / 1e9
     srv = hm.Server(pool, slots=4, max_batch_packets=4096, max_batch_codewords=1 << 26,
-                    output_pool_bytes=4 << 30, auto_release=True)
+                    output_pool_bytes=32 << 30, auto_release=True)
     out = []
     try:
         for rho in loads:
@@ -276,7 +276,7 @@ def serving_leg(dev, plain_gBps_per_r: dict, loads, n_requests: int, warm: int):
         torch.cuda.empty_cache()
     return {"workload": "256 SDR streams, r = 4 + stream % 4, request sizes log-uniform in [256, 2^18] "
                         "codewords, 10% single-bit errors, Poisson arrivals; 4 batches in flight; output "
-                        "pool 4 GiB", "points": out}
+                        "pool (device-memory admission cap) 32 GiB", "points": out}
 
 
 def latency_leg(dev, reps: int):
@@ -371,6 +371,40 @@ def host_leg(dev, reps: int):
             "d2h_GBps": round((chunk * (k + 8) / 8) / pr / 1e6, 1),
             "eq1_predicted_speedup": round(eq1, 3), "stage_bound_speedup": round(pipe, 3),
             "payload_Gbps_async": round(n * k / t_async / 1e9, 1)}
+
+
+def sizes_leg(dev):
+    """Plain decode over the packet-size sweep 2^10..2^28 codewords of
+    Hamming(15,11), (31,26), (63,57): each size decodes a prefix of one
+    device-generated 2^28-codeword packet (10% single-bit errors)."""
+    import torch
+
+    import paper_1412_6862_amd as hm
+    import synth
+
+    stream = torch.cuda.current_stream()
+    rows = []
+    for r in WORKLOAD_R:
+        nmax = 1 << 28
+        seed = synth.workload_seed("bench-sizes", r)
+        cw = hm.encode(synth.message_stream_torch(seed, nmax, r, dev), nmax, r)
+        cw ^= synth.flip_masks_torch(seed, nmax, r, P_SINGLE, dev)
+        data = torch.empty(hm.hamming_data_bytes(nmax, r), dtype=torch.uint8, device=dev)
+        ep = torch.empty(nmax, dtype=torch.uint8, device=dev)
+        k = hm.hamming_message_bits(r)
+        for lg in range(10, 29, 2):
+            n = 1 << lg
+            reps = 200 if lg <= 20 else 20
+            t = time_events(lambda: hm.hamming_decode(cw, n, r, data, ep, stream), stream, 3, reps)
+            med = t[len(t) // 2]
+            algo = algorithmic_bytes_per_codeword(r) * n
+            rows.append({"r": r, "n_cw": n, "us_p50": round(med * 1e3, 2),
+                         "payload_Gbps": round(n * k / med / 1e6, 1),
+                         "frac_hbm": round(algo / med / 1e6 / HBM_PEAK_GBPS, 4)})
+        del cw, data, ep
+        torch.cuda.empty_cache()
+    return {"workload": "plain decode, packet sizes 2^10..2^28 codewords (every 4x) of r = 4, 5, 6, "
+                        "10% single-bit errors", "rows": rows}
 
 
 def planes_leg(dev, reps: int):
@@ -528,9 +562,9 @@ def main() -> int:
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner before timing instead of loading the committed shapes")
     ap.add_argument("--seg-packets", type=int, default=1 << 19)
-    ap.add_argument("--legs", default="latency,r7,batch,serve,host,seg,planes",
+    ap.add_argument("--legs", default="latency,sizes,r7,batch,serve,host,seg,planes",
                     help="extra legs after the plain one (which gives the reported value): "
-                         "comma-separated subset of latency,r7,batch,serve,host,seg,planes, or none")
+                         "comma-separated subset of latency,sizes,r7,batch,serve,host,seg,planes, or none")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (counter calibration)")
     args = ap.parse_args()
@@ -657,6 +691,8 @@ def main() -> int:
     torch.cuda.empty_cache()
     if "latency" in legs:
         out["latency_hamming74"] = latency_leg(dev, 1000)
+    if "sizes" in legs:
+        out["size_sweep"] = sizes_leg(dev)
     if "r7" in legs:
         out["hamming127"] = hamming127_leg(dev, 20)
     if "batch" in legs:

@@ -202,3 +202,32 @@ def test_tuner_applies_and_persists_valid_shapes(gpu_device, tmp_path):
         for r in range(3, 8):
             hm.hamming_plain_config_set(r, *old_plain[r])
         hm.hamming_batch_config_set(*old_batch)
+
+
+@pytest.mark.parametrize("r", [4, 6])
+def test_plain_parity_2p28_sampled(gpu_device, r):
+    """The largest packet of the size sweep, 2^28 codewords, generated and
+    encoded on the device; slices are regenerated on the CPU from the same
+    counter-based streams and checked against the oracle one by one."""
+    import torch
+
+    n_cw, p = 1 << 28, 0.1
+    seed = synth.workload_seed("gpu-2p28", r)
+    cw = hm.encode(synth.message_stream_torch(seed, n_cw, r, gpu_device), n_cw, r)
+    cw ^= synth.flip_masks_torch(seed, n_cw, r, p, gpu_device)
+    data, ep = hm.decode(cw, r)
+    torch.cuda.synchronize()
+    del cw
+    k = hm.hamming_message_bits(r)
+    rng = np.random.default_rng(r)
+    firsts = [0, n_cw // 2, n_cw - 4096] + [int(x) // 64 * 64 for x in rng.integers(0, n_cw - 4096, 5)]
+    for first in firsts:
+        n = 4096
+        y = oracle.encode(synth.message_stream_slice(seed, first, n, r), n, r)
+        p1, p2 = synth.error_positions(seed, n, r, p_single=p, start=first)
+        y ^= synth.flip_masks(p1, p2, r)
+        d_ref, e_ref = oracle.decode(y, r)
+        b0 = first * k // 8
+        assert np.array_equal(data[b0:b0 + d_ref.size].cpu().numpy(), d_ref), first
+        assert np.array_equal(ep[first:first + n].cpu().numpy(), e_ref), first
+    assert data.numel() == hm.hamming_data_bytes(n_cw, r)
