@@ -349,15 +349,21 @@ def host_leg(dev, reps: int):
 
     def run(mode, times=False):
         t0 = time.perf_counter()
-        st = hm.hamming_decode_host(cw, n, r, data, ep, chunk, mode, streams, ws, wsb, times=times)
+        if mode == hm.HAMMING_TRANSFER_MAPPED:
+            st = hm.hamming_decode_host(cw, n, r, data, ep, chunk, mode, streams, None, 0, times=times)
+        else:
+            st = hm.hamming_decode_host(cw, n, r, data, ep, chunk, mode, streams, ws, wsb, times=times)
         return time.perf_counter() - t0, st
 
     run(hm.HAMMING_TRANSFER_SYNC)
     run(hm.HAMMING_TRANSFER_ASYNC)
+    run(hm.HAMMING_TRANSFER_MAPPED)
     sync = [run(hm.HAMMING_TRANSFER_SYNC, True) for _ in range(reps)]
     asyn = [run(hm.HAMMING_TRANSFER_ASYNC)[0] for _ in range(reps)]
+    mapd = [run(hm.HAMMING_TRANSFER_MAPPED)[0] for _ in range(reps)]
     t_sync = float(np.median([s[0] for s in sync]))
     t_async = float(np.median(asyn))
+    t_mapped = float(np.median(mapd))
     ps, dke, pr = (float(np.median([s[1][i] for s in sync])) / n_chunks for i in range(3))
     eq1 = n_chunks * (ps + dke + pr) / (ps + n_chunks * dke + pr)
     stage = max(ps, dke, pr)
@@ -366,11 +372,14 @@ def host_leg(dev, reps: int):
                         "codewords, %d streams, 10%% single-bit errors" % (n_chunks, streams),
             "sync_ms": round(t_sync * 1e3, 2), "async_ms": round(t_async * 1e3, 2),
             "async_speedup": round(t_sync / t_async, 3),
+            "mapped_ms": round(t_mapped * 1e3, 2), "mapped_speedup": round(t_sync / t_mapped, 3),
+            "mapped_link_GBps": round((n * 8 + n * (k + 8) / 8) / t_mapped / 1e9, 1),
             "chunk_ms": {"h2d": round(ps, 3), "decode": round(dke, 4), "d2h": round(pr, 3)},
             "h2d_GBps": round(chunk * 8 / ps / 1e6, 1),
             "d2h_GBps": round((chunk * (k + 8) / 8) / pr / 1e6, 1),
             "eq1_predicted_speedup": round(eq1, 3), "stage_bound_speedup": round(pipe, 3),
-            "payload_Gbps_async": round(n * k / t_async / 1e9, 1)}
+            "payload_Gbps_async": round(n * k / t_async / 1e9, 1),
+            "payload_Gbps_mapped": round(n * k / t_mapped / 1e9, 1)}
 
 
 def sizes_leg(dev):

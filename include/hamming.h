@@ -330,10 +330,12 @@ int hamming_encode_segmented(const uint64_t *msg_arena, uint64_t msg_words, cons
 /* ---- host-resident packets: transfer pipeline ------------------------------ */
 
 /* Transfer scheduling of hamming_decode_host (Sec. III.B): one chunk after
- * another on one stream, or chunks spread over several streams so that
+ * another on one stream (SYNC), or chunks spread over several streams so that
  * host-to-device copies, decodes and device-to-host copies of different chunks
- * overlap. */
-enum hamming_transfer_mode { HAMMING_TRANSFER_SYNC = 0, HAMMING_TRANSFER_ASYNC = 1 };
+ * overlap (ASYNC).  MAPPED uses no copies: the decode kernel reads the
+ * received words from, and writes its results to, pinned host memory through
+ * its device mapping, so both link directions carry data at once. */
+enum hamming_transfer_mode { HAMMING_TRANSFER_SYNC = 0, HAMMING_TRANSFER_ASYNC = 1, HAMMING_TRANSFER_MAPPED = 2 };
 
 /* Device workspace bytes hamming_decode_host needs for chunks of chunk_cw
  * codewords of code r on `streams` streams; 0 for invalid arguments. */
@@ -353,7 +355,11 @@ uint64_t hamming_host_workspace_bytes(uint64_t chunk_cw, int r, uint32_t streams
  *                     then serialise.
  *   host_data_out   : host, hamming_data_bytes(n_cw, r) bytes.
  *   host_errpos_out : host, n_cw bytes, or NULL.
- *   mode            : HAMMING_TRANSFER_SYNC or HAMMING_TRANSFER_ASYNC.
+ *   mode            : HAMMING_TRANSFER_SYNC, _ASYNC or _MAPPED.  MAPPED needs
+ *                     all three host buffers in pinned, device-mapped memory
+ *                     (hipHostMalloc); any other memory is rejected with
+ *                     HAMMING_EINVAL before anything runs.  MAPPED ignores
+ *                     chunk_cw, streams and the workspace (may be NULL).
  *   streams         : streams used by the asynchronous mode (1..8); the
  *                     synchronous mode uses one.
  *   workspace       : device, hamming_host_workspace_bytes(chunk_cw, r,
@@ -361,7 +367,8 @@ uint64_t hamming_host_workspace_bytes(uint64_t chunk_cw, int r, uint32_t streams
  *   times_ms        : NULL, or double[3] receiving the summed milliseconds of
  *                     host-to-device copies, decodes and device-to-host copies
  *                     (per-operation events; meaningful in the synchronous
- *                     mode, where the operations do not overlap).
+ *                     mode, where the operations do not overlap; MAPPED
+ *                     reports the whole kernel as the decode time).
  * Returns HAMMING_OK, HAMMING_EINVAL, HAMMING_EALIGN, HAMMING_ERANGE,
  * HAMMING_ENOMEM (workspace too small) or HAMMING_EDEVICE.
  */

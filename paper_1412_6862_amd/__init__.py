@@ -111,6 +111,7 @@ HAMMING_SEG_INVALID = 0xFF
 
 HAMMING_TRANSFER_SYNC = 0
 HAMMING_TRANSFER_ASYNC = 1
+HAMMING_TRANSFER_MAPPED = 2
 
 HAMMING_NO_ERRPOS = (1 << 64) - 1
 HAMMING_MAX_BATCH = 1 << 24
@@ -378,8 +379,9 @@ def encode(messages, n_cw: int, r: int, stream=None):
 
 def decode_host(codewords, r: int, chunk_cw: int = 1 << 22, mode: int = HAMMING_TRANSFER_ASYNC,
                 streams: int = 3, errpos: bool = True, device=None):
-    """Decode a host tensor of codewords (pin it for overlapping copies);
-    returns host (data, errpos) tensors, pinned when the input is."""
+    """Decode a host tensor of codewords (pin it for overlapping copies; the
+    mapped mode requires it); returns host (data, errpos) tensors, pinned when
+    the input is."""
     import torch
 
     if codewords.device.type != "cpu":
@@ -389,10 +391,13 @@ def decode_host(codewords, r: int, chunk_cw: int = 1 << 22, mode: int = HAMMING_
     pin = cw.is_pinned()
     data = torch.empty(hamming_data_bytes(n_cw, r), dtype=torch.uint8, pin_memory=pin)
     ep = torch.empty(n_cw, dtype=torch.uint8, pin_memory=pin) if errpos else None
-    wsb = hamming_host_workspace_bytes(chunk_cw, r, streams)
-    if wsb == 0:
-        raise HammingError(HAMMING_EINVAL, "hamming_host_workspace_bytes")
-    ws = torch.empty(wsb, dtype=torch.uint8, device=device or torch.device("cuda"))
+    if mode == HAMMING_TRANSFER_MAPPED:
+        ws, wsb = None, 0
+    else:
+        wsb = hamming_host_workspace_bytes(chunk_cw, r, streams)
+        if wsb == 0:
+            raise HammingError(HAMMING_EINVAL, "hamming_host_workspace_bytes")
+        ws = torch.empty(wsb, dtype=torch.uint8, device=device or torch.device("cuda"))
     hamming_decode_host(cw, n_cw, r, data, ep, chunk_cw, mode, streams, ws, wsb)
     return data, ep
 

@@ -1,8 +1,9 @@
 // Decode of host-resident packets with copies scheduled as in Sec. III.B:
 // synchronous (copy in, decode, copy out, chunk after chunk) or asynchronous
 // (chunks spread over several streams so that copies and decodes of different
-// chunks overlap, the pipelined transfer of Fig. 5 / Eq. 1).  Host code only;
-// the decodes are hamming_decode's kernels.
+// chunks overlap, the pipelined transfer of Fig. 5 / Eq. 1), plus a mapped
+// mode in which the kernel itself reads and writes pinned host memory.  Host
+// code only; the decodes are hamming_decode's kernels.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -45,6 +46,48 @@ struct Timers {
     }
 };
 
+// Device address of pinned, device-mapped host memory, or nullptr for
+// anything else (pageable memory, device memory, unknown pointers).
+void* mapped_address(const void* p)
+{
+    hipPointerAttribute_t at;
+    if (!p || hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (at.type != hipMemoryTypeHost || !at.devicePointer || !at.hostPointer) return nullptr;
+    const char* hp = static_cast<const char*>(at.hostPointer);
+    const char* q = static_cast<const char*>(p);
+    return static_cast<char*>(at.devicePointer) + (q - hp);
+}
+
+// Mapped mode: the decode kernel reads the received words from host memory
+// and writes the results to host memory itself, so the two PCIe directions
+// are in use at the same time without copy engines.
+int decode_mapped(const uint64_t* host_cw, uint64_t n_cw, int r, void* host_data_out, uint8_t* host_errpos_out,
+                  double* times_ms)
+{
+    const void* dcw = mapped_address(host_cw);
+    void* ddata = mapped_address(host_data_out);
+    void* dep = host_errpos_out ? mapped_address(host_errpos_out) : nullptr;
+    if (!dcw || !ddata || (host_errpos_out && !dep)) return HAMMING_EINVAL;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return HAMMING_EDEVICE;
+    Timers tm;
+    int rc = tm.ok ? HAMMING_OK : HAMMING_EDEVICE;
+    if (rc == HAMMING_OK && times_ms) (void)hipEventRecord(tm.e[0], s);
+    if (rc == HAMMING_OK)
+        rc = hamming_decode(static_cast<const uint64_t*>(dcw), n_cw, r, ddata, static_cast<uint8_t*>(dep), s);
+    if (rc == HAMMING_OK && times_ms) (void)hipEventRecord(tm.e[1], s);
+    if (hipStreamSynchronize(s) != hipSuccess && rc == HAMMING_OK) rc = HAMMING_EDEVICE;
+    if (rc == HAMMING_OK && times_ms) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, tm.e[0], tm.e[1]) == hipSuccess) times_ms[1] = ms;
+    }
+    (void)hipStreamDestroy(s);
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -61,8 +104,18 @@ int hamming_decode_host(const uint64_t* host_cw, uint64_t n_cw, int r, void* hos
                         uint8_t* host_errpos_out, uint64_t chunk_cw, int mode, uint32_t streams, void* workspace,
                         uint64_t workspace_bytes, double* times_ms)
 {
-    if (r < 3 || r > 7 || (mode != HAMMING_TRANSFER_SYNC && mode != HAMMING_TRANSFER_ASYNC)) return HAMMING_EINVAL;
+    if (r < 3 || r > 7 ||
+        (mode != HAMMING_TRANSFER_SYNC && mode != HAMMING_TRANSFER_ASYNC && mode != HAMMING_TRANSFER_MAPPED))
+        return HAMMING_EINVAL;
     if (n_cw > HAMMING_MAX_CODEWORDS) return HAMMING_ERANGE;
+    if (mode == HAMMING_TRANSFER_MAPPED) {
+        if (times_ms) times_ms[0] = times_ms[1] = times_ms[2] = 0.0;
+        if (n_cw == 0) return HAMMING_OK;
+        if (!host_cw || !host_data_out) return HAMMING_EINVAL;
+        if ((reinterpret_cast<uintptr_t>(host_cw) & 7u) || (reinterpret_cast<uintptr_t>(host_data_out) & 7u))
+            return HAMMING_EALIGN;
+        return decode_mapped(host_cw, n_cw, r, host_data_out, host_errpos_out, times_ms);
+    }
     if (chunk_cw == 0 || chunk_cw % 64 || streams < 1 || streams > kMaxStreams) return HAMMING_EINVAL;
     if (times_ms) times_ms[0] = times_ms[1] = times_ms[2] = 0.0;
     if (n_cw == 0) return HAMMING_OK;

@@ -283,3 +283,15 @@ def test_planes_words_and_validation_codes():
     assert dec(pl=A + 4) == hm.HAMMING_EALIGN and dec(d=A + 4) == hm.HAMMING_EALIGN
     assert conv(cw=A + 4) == hm.HAMMING_EALIGN and conv(pl=A + 2) == hm.HAMMING_EALIGN
     assert dec(n=0, pl=0, d=0) == hm.HAMMING_OK and conv(n=0, cw=0, pl=0) == hm.HAMMING_OK
+
+
+def test_host_mapped_mode_argument_checks():
+    lib = hm.library()
+    A = 1 << 20
+    M = hm.HAMMING_TRANSFER_MAPPED
+    assert lib.hamming_decode_host(A, 10, 4, A, None, 64, 3, 1, None, 0, None) == hm.HAMMING_EINVAL
+    assert lib.hamming_decode_host(0, 10, 4, A, None, 64, M, 1, None, 0, None) == hm.HAMMING_EINVAL
+    assert lib.hamming_decode_host(A, 10, 4, 0, None, 64, M, 1, None, 0, None) == hm.HAMMING_EINVAL
+    assert lib.hamming_decode_host(A + 4, 10, 4, A, None, 64, M, 1, None, 0, None) == hm.HAMMING_EALIGN
+    assert lib.hamming_decode_host(A, 10, 9, A, None, 64, M, 1, None, 0, None) == hm.HAMMING_EINVAL
+    assert lib.hamming_decode_host(0, 0, 4, 0, None, 0, M, 0, None, 0, None) == hm.HAMMING_OK

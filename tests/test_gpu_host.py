@@ -86,3 +86,37 @@ def test_host_pipeline_convenience_matches_device_decode(gpu_device):
     d_dev, e_dev = hm.decode(cw.to(gpu_device), r)
     torch.cuda.synchronize()
     assert torch.equal(d_host, d_dev.cpu()) and torch.equal(e_host, e_dev.cpu())
+
+
+@pytest.mark.parametrize("r", [3, 6, 7])
+def test_host_mapped_mode_parity(gpu_device, r):
+    import torch
+
+    n_cw = 70000 + 13
+    y = received_words(synth.workload_seed("gpu-host-mapped", r), n_cw, r, p_single=0.3, p_double=0.1)
+    d_ref, e_ref = oracle.decode(y, r)
+    cw = _host(y, True)
+    data, ep = hm.decode_host(cw, r, mode=hm.HAMMING_TRANSFER_MAPPED, device=gpu_device)
+    assert np.array_equal(data.numpy(), d_ref) and np.array_equal(ep.numpy(), e_ref)
+    # interior pointers of pinned allocations map too
+    big = torch.full((d_ref.size + 64,), 0xA5, dtype=torch.uint8, pin_memory=True)
+    hm.hamming_decode_host(cw, n_cw, r, big[8:8 + d_ref.size], None, 64, hm.HAMMING_TRANSFER_MAPPED, 1, None, 0)
+    b = big.numpy()
+    assert np.array_equal(b[8:8 + d_ref.size], d_ref) and (b[:8] == 0xA5).all() and (b[8 + d_ref.size:] == 0xA5).all()
+
+
+def test_host_mapped_mode_rejects_unmapped_memory(gpu_device):
+    import torch
+
+    n_cw = 4096
+    y = received_words(synth.workload_seed("gpu-host-mapped-bad", 4), n_cw, 4)
+    pageable = _host(y, False)
+    pinned = _host(y, True)
+    out_pinned = torch.empty(hm.hamming_data_bytes(n_cw, 4), dtype=torch.uint8, pin_memory=True)
+    out_pageable = torch.empty(hm.hamming_data_bytes(n_cw, 4), dtype=torch.uint8)
+    on_device = torch.empty(n_cw, dtype=torch.int64, device=gpu_device)
+    M = hm.HAMMING_TRANSFER_MAPPED
+    for cw, out in ((pageable, out_pinned), (pinned, out_pageable), (on_device, out_pinned)):
+        with pytest.raises(hm.HammingError) as ei:
+            hm.hamming_decode_host(cw, n_cw, 4, out, None, 64, M, 1, None, 0)
+        assert ei.value.status == hm.HAMMING_EINVAL
