@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "hamming.h"
 #include "tile.h"
 
@@ -115,16 +117,28 @@ __device__ __forceinline__ uint32_t word_syndrome(const uint64_t* L, uint32_t o,
     return v;
 }
 
+// Barrier of the threads that decode one packet: one wave, or the workgroup.
+template <uint32_t GROUP>
+__device__ __forceinline__ void group_sync()
+{
+    if constexpr (GROUP == 64) {
+        wave_sync();
+    } else {
+        __syncthreads();
+    }
+}
+
 // Syndromes of all segments: the position words of every segment form one
-// flat list dealt to the lanes (lane L takes words L, L+64, ...); each lane
+// flat list dealt to the GROUP threads (thread L takes words L, L+GROUP, ...); each
 // walks its (segment, word) position forward and XORs its words'
 // contributions into the segment's accumulator in LDS.  S must be zero and
 // visible on entry; the result is visible to the whole wave on return.
+template <uint32_t GROUP>
 __device__ __forceinline__ void all_syndromes(const uint64_t* L, const Layout& Lo, uint32_t* S, uint32_t lane)
 {
     const uint32_t words = Lo.syndrome_words();
-    uint32_t i = 0, w = lane, nw = Lo.t > 0 && Lo.rem > 0 ? Lo.nwA : Lo.nwB;
-    for (uint32_t g = lane; g < words; g += 64) {
+    uint32_t i = 0, w = lane, nw = Lo.rem > 0 ? Lo.nwA : Lo.nwB;
+    for (uint32_t g = lane; g < words; g += GROUP) {
         while (w >= nw) {          // move to the segment holding word g
             w -= nw;
             ++i;
@@ -132,9 +146,9 @@ __device__ __forceinline__ void all_syndromes(const uint64_t* L, const Layout& L
         }
         const uint32_t v = word_syndrome(L, Lo.o(i), Lo.n(i), w);
         if (v) atomicXor(&S[i], v);
-        w += 64;
+        w += GROUP;
     }
-    wave_sync();
+    group_sync<GROUP>();
 }
 
 // The message positions below 64 (3, 5..7, 9..15, 17..31, 33..63) carry a
@@ -173,16 +187,13 @@ struct SegArgs {
     uint32_t slice_words;      // per-wave LDS slice (syndrome accumulators excluded)
 };
 
-__global__ __launch_bounds__(64 * kSegWaves) void seg_decode_kernel(SegArgs a)
+// Decode packet pk with GROUP threads (gl = 0..GROUP-1); L is the packet's LDS
+// slice and S its syndrome accumulators.  The checksum owners gl < t are all
+// in the first wave (t <= 32).  Every thread of the group takes the same
+// branches at the barriers.
+template <uint32_t GROUP>
+__device__ __forceinline__ void decode_packet(const SegArgs& a, uint64_t pk, uint32_t gl, uint64_t* L, uint32_t* S)
 {
-    extern __shared__ uint64_t lds[];
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint64_t pk = uint64_t(blockIdx.x) * kSegWaves + wib;
-    if (pk >= a.n_packets) return;
-    uint64_t* L = lds + wib * (a.slice_words + kSynWords);
-    uint32_t* S = reinterpret_cast<uint32_t*>(L + a.slice_words);
-
     const hamming_seg_packet d = a.descs[pk];
     const uint32_t M = d.msg_bytes, t = d.t;
     Layout Lo;
@@ -192,22 +203,22 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_decode_kernel(SegArgs a)
                     d.msg_word_off <= a.msg_words && mw <= a.msg_words - d.msg_word_off &&
                     (!a.syndromes || (d.seg_off <= a.syndrome_count && t <= a.syndrome_count - d.seg_off));
     if (!ok) {
-        if (a.status && lane == 0) a.status[pk] = HAMMING_SEG_INVALID;
+        if (a.status && gl == 0) a.status[pk] = HAMMING_SEG_INVALID;
         return;
     }
 
     const uint64_t* src = a.enc + d.enc_word_off;
-    for (uint32_t w = lane; w < ew; w += 64) L[w] = __builtin_nontemporal_load(src + w);
-    if (lane < 2) L[ew + lane] = 0;
-    if (lane < HAMMING_SEG_MAX_T) S[lane] = 0;
-    wave_sync();
+    for (uint32_t w = gl; w < ew; w += GROUP) L[w] = __builtin_nontemporal_load(src + w);
+    if (gl < 2) L[ew + gl] = 0;
+    if (gl < HAMMING_SEG_MAX_T) S[gl] = 0;
+    group_sync<GROUP>();
 
-    all_syndromes(L, Lo, S, lane);
-    const uint32_t my_s = lane < t ? S[lane] : 0u;
+    all_syndromes<GROUP>(L, Lo, S, gl);
+    const uint32_t my_s = gl < t ? S[gl] : 0u;
 
     uint32_t st = 0;
-    if (lane < t) {
-        const uint32_t o = Lo.o(lane), n = Lo.n(lane);
+    if (gl < t) {
+        const uint32_t o = Lo.o(gl), n = Lo.n(gl);
         if (my_s >= 1 && my_s <= n) {
             const uint32_t bit = o + my_s - 1;
             atomicXor(reinterpret_cast<unsigned long long*>(&L[bit >> 6]), 1ull << (bit & 63));
@@ -215,18 +226,18 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_decode_kernel(SegArgs a)
         } else if (my_s > n) {
             st = 2;
         }
-        if (a.syndromes) a.syndromes[d.seg_off + lane] = uint16_t(my_s);
+        if (a.syndromes) a.syndromes[d.seg_off + gl] = uint16_t(my_s);
     }
     const uint64_t any2 = __ballot(st == 2), any1 = __ballot(st == 1);
-    if (a.status && lane == 0) a.status[pk] = any2 ? 2 : (any1 ? 1 : 0);
-    wave_sync();
+    if (a.status && gl == 0) a.status[pk] = any2 ? 2 : (any1 ? 1 : 0);
+    group_sync<GROUP>();
 
-    // merge: lane-owned 64-bit words of the packet's message
+    // merge: thread-owned 64-bit words of the packet's message
     const uint32_t nbits = 8u * M;
     uint64_t* dst = a.msg + d.msg_word_off;
-    uint32_t i = Lo.seg_of_msg(64u * lane);
+    uint32_t i = Lo.seg_of_msg(64u * gl);
     uint32_t K = Lo.K(i), k = Lo.k(i), R = Lo.o(i) - K;       // R: checksum bits before segment i
-    for (uint32_t ow = lane; ow < mw; ow += 64) {
+    for (uint32_t ow = gl; ow < mw; ow += GROUP) {
         uint32_t m = 64u * ow;
         const uint32_t end = min(m + 64u, nbits);
         uint64_t acc = 0;
@@ -256,6 +267,26 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_decode_kernel(SegArgs a)
         }
         __builtin_nontemporal_store(acc, dst + ow);
     }
+}
+
+// Throughput form: four packets per block, one wave each.
+__global__ __launch_bounds__(64 * kSegWaves) void seg_decode_kernel(SegArgs a)
+{
+    extern __shared__ uint64_t lds[];
+    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t pk = uint64_t(blockIdx.x) * kSegWaves + wib;
+    if (pk >= a.n_packets) return;
+    uint64_t* L = lds + wib * (a.slice_words + kSynWords);
+    decode_packet<64>(a, pk, threadIdx.x & 63u, L, reinterpret_cast<uint32_t*>(L + a.slice_words));
+}
+
+// Latency form: one packet per block, all four waves on it.
+__global__ __launch_bounds__(64 * kSegWaves) void seg_decode_wide_kernel(SegArgs a)
+{
+    extern __shared__ uint64_t lds[];
+    const uint64_t pk = blockIdx.x;
+    if (pk >= a.n_packets) return;
+    decode_packet<64 * kSegWaves>(a, pk, threadIdx.x, lds, reinterpret_cast<uint32_t*>(lds + a.slice_words));
 }
 
 __global__ __launch_bounds__(64 * kSegWaves) void seg_encode_kernel(SegArgs a)
@@ -316,7 +347,7 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_encode_kernel(SegArgs a)
     wave_sync();
 
     // checksum position 2^j takes bit j of the syndrome of the message bits alone
-    all_syndromes(E, Lo, S, lane);
+    all_syndromes<64>(E, Lo, S, lane);
     if (lane < t) {
         const uint32_t s = S[lane], o = Lo.o(lane);
         for (uint32_t j = 0; s >> j; ++j) {
@@ -329,6 +360,11 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_encode_kernel(SegArgs a)
     uint64_t* dst = const_cast<uint64_t*>(a.enc) + d.enc_word_off;
     for (uint32_t w = lane; w < ew; w += 64) __builtin_nontemporal_store(E[w], dst + w);
 }
+
+// Batches up to this many packets use one workgroup per packet: fewer
+// packets than the GPU has wave slots, so shorter per-packet latency wins.
+constexpr uint32_t kWideMaxPackets = 2048;
+std::atomic<int> g_seg_mode{HAMMING_SEG_AUTO};
 
 int check_common(const void* enc, const void* descs, uint32_t n_packets, const void* msg, uint32_t max_msg_bytes)
 {
@@ -363,6 +399,20 @@ int64_t hamming_seg_layout(uint32_t msg_bytes, uint32_t t, uint32_t* k_out, uint
     return total;
 }
 
+int hamming_seg_config_set(int mode)
+{
+    if (mode < HAMMING_SEG_AUTO || mode > HAMMING_SEG_PACKET_PER_BLOCK) return HAMMING_EINVAL;
+    g_seg_mode.store(mode);
+    return HAMMING_OK;
+}
+
+int hamming_seg_config_get(int* mode)
+{
+    if (!mode) return HAMMING_EINVAL;
+    *mode = g_seg_mode.load();
+    return HAMMING_OK;
+}
+
 int hamming_decode_segmented(const uint64_t* enc_arena, uint64_t enc_words, const hamming_seg_packet* descs,
                              uint32_t n_packets, uint32_t max_msg_bytes, uint64_t* msg_arena, uint64_t msg_words,
                              uint16_t* syndromes, uint64_t syndrome_count, uint8_t* status, hipStream_t stream)
@@ -372,9 +422,16 @@ int hamming_decode_segmented(const uint64_t* enc_arena, uint64_t enc_words, cons
     if (syndromes && (reinterpret_cast<uintptr_t>(syndromes) & 1u)) return HAMMING_EALIGN;
     SegArgs a{enc_arena, enc_words, descs, n_packets, max_msg_bytes, msg_arena, msg_words,
               syndromes, syndromes ? syndrome_count : 0, status, enc_slice_words(max_msg_bytes)};
-    const size_t lds = size_t(kSegWaves) * (a.slice_words + kSynWords) * 8;
-    const uint32_t blocks = (n_packets + kSegWaves - 1) / kSegWaves;
-    hipLaunchKernelGGL(seg_decode_kernel, dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
+    const int mode = g_seg_mode.load();
+    const bool wide = mode == HAMMING_SEG_PACKET_PER_BLOCK || (mode == HAMMING_SEG_AUTO && n_packets <= kWideMaxPackets);
+    if (wide) {
+        const size_t lds = size_t(a.slice_words + kSynWords) * 8;
+        hipLaunchKernelGGL(seg_decode_wide_kernel, dim3(n_packets), dim3(64 * kSegWaves), lds, stream, a);
+    } else {
+        const size_t lds = size_t(kSegWaves) * (a.slice_words + kSynWords) * 8;
+        const uint32_t blocks = (n_packets + kSegWaves - 1) / kSegWaves;
+        hipLaunchKernelGGL(seg_decode_kernel, dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
+    }
     return hipGetLastError() == hipSuccess ? HAMMING_OK : HAMMING_EDEVICE;
 }
 

@@ -295,3 +295,16 @@ def test_host_mapped_mode_argument_checks():
     assert lib.hamming_decode_host(A + 4, 10, 4, A, None, 64, M, 1, None, 0, None) == hm.HAMMING_EALIGN
     assert lib.hamming_decode_host(A, 10, 9, A, None, 64, M, 1, None, 0, None) == hm.HAMMING_EINVAL
     assert lib.hamming_decode_host(0, 0, 4, 0, None, 0, M, 0, None, 0, None) == hm.HAMMING_OK
+
+
+def test_segmented_mode_config_roundtrip():
+    old = hm.hamming_seg_config_get()
+    try:
+        for m in (hm.HAMMING_SEG_WAVE_PER_PACKET, hm.HAMMING_SEG_PACKET_PER_BLOCK, hm.HAMMING_SEG_AUTO):
+            hm.hamming_seg_config_set(m)
+            assert hm.hamming_seg_config_get() == m
+        for bad in (-1, 3):
+            with pytest.raises(hm.HammingError):
+                hm.hamming_seg_config_set(bad)
+    finally:
+        hm.hamming_seg_config_set(old)

@@ -13,6 +13,16 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
+MODES = [1, 2]   # one wave per packet, one workgroup per packet
+
+
+@pytest.fixture
+def seg_mode(request):
+    old = hm.hamming_seg_config_get()
+    hm.hamming_seg_config_set(request.param)
+    yield request.param
+    hm.hamming_seg_config_set(old)
+
 
 def _received(seed, P, msg_bytes, t, row_bytes, p_single, p_double):
     """Oracle-encoded random packets with per-segment channel flips."""
@@ -50,21 +60,24 @@ def _check_batch(device, P, msg_bytes, t, p_single=0.4, p_double=0.2, garbage=Tr
     return st_ref
 
 
+@pytest.mark.parametrize("seg_mode", MODES, indirect=True)
 @pytest.mark.parametrize("msg_bytes", synth.PAPER_PACKET_BYTES)
 @pytest.mark.parametrize("t", synth.PAPER_SEGMENTS)
-def test_segmented_parity_papers_packet_shapes(gpu_device, msg_bytes, t):
+def test_segmented_parity_papers_packet_shapes(gpu_device, seg_mode, msg_bytes, t):
     st = _check_batch(gpu_device, 301, msg_bytes, t)
     assert (st == 1).any() and (st == 2).any()       # clean packets: see the error-extremes test
 
 
 @pytest.mark.parametrize("msg_bytes,t", [(1, 1), (1, 3), (1, 8), (7, 8), (13, 5), (3, 24), (57, 8), (15, 1),
                                          (4096, 1), (4096, 32), (1000, 32), (8, 1), (9, 1), (255, 7)])
-def test_segmented_parity_edge_shapes(gpu_device, msg_bytes, t):
+@pytest.mark.parametrize("seg_mode", MODES, indirect=True)
+def test_segmented_parity_edge_shapes(gpu_device, seg_mode, msg_bytes, t):
     _check_batch(gpu_device, 130, msg_bytes, t)
 
 
 @pytest.mark.parametrize("p_single,p_double", [(0.0, 0.0), (1.0, 0.0), (0.0, 1.0)])
-def test_segmented_parity_error_extremes(gpu_device, p_single, p_double):
+@pytest.mark.parametrize("seg_mode", MODES, indirect=True)
+def test_segmented_parity_error_extremes(gpu_device, seg_mode, p_single, p_double):
     st = _check_batch(gpu_device, 200, 1200, 4, p_single, p_double)
     if p_single == 0 and p_double == 0:
         assert not st.any()
@@ -95,7 +108,8 @@ def test_segmented_encoder_parity(gpu_device, msg_bytes, t):
     assert np.array_equal(got, msgs) and not b.status.cpu().numpy().any()
 
 
-def test_segmented_mixed_shapes_offsets_and_invalid_descriptors(gpu_device):
+@pytest.mark.parametrize("seg_mode", MODES, indirect=True)
+def test_segmented_mixed_shapes_offsets_and_invalid_descriptors(gpu_device, seg_mode):
     import torch
 
     rng = np.random.default_rng(7)
@@ -154,7 +168,8 @@ def test_segmented_mixed_shapes_offsets_and_invalid_descriptors(gpu_device):
     assert (syn[~written_syn] == 0x7777).all()
 
 
-def test_segmented_max_msg_bytes_bound_rejects_longer_packets(gpu_device):
+@pytest.mark.parametrize("seg_mode", MODES, indirect=True)
+def test_segmented_max_msg_bytes_bound_rejects_longer_packets(gpu_device, seg_mode):
     import torch
 
     b = hm.SegmentedBatch(8, 800, 3, device=gpu_device)
