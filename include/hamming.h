@@ -316,14 +316,14 @@ int hamming_decode_segmented(const uint64_t *enc_arena, uint64_t enc_words, cons
                              uint32_t n_packets, uint32_t max_msg_bytes, uint64_t *msg_arena, uint64_t msg_words,
                              uint16_t *syndromes, uint64_t syndrome_count, uint8_t *status, hipStream_t stream);
 
-/* Work assignment of hamming_decode_segmented (no effect on results):
- * HAMMING_SEG_AUTO picks one workgroup per packet for batches of at most 2048
- * packets (latency) and one wave per packet above (throughput); the other
- * two values force one form.  Process-wide.  Returns HAMMING_OK or
+/* Work assignment of hamming_decode_segmented (no effect on results): the
+ * threads that cooperate on one packet, 16 or 32 (part of a wave), 64 (a
+ * wave) or 256 (a workgroup).  0 lets the library choose: a workgroup per
+ * packet for batches of at most 2048 packets (latency), else a group sized to
+ * max_msg_bytes (throughput).  Process-wide.  Returns HAMMING_OK or
  * HAMMING_EINVAL. */
-enum hamming_seg_mode { HAMMING_SEG_AUTO = 0, HAMMING_SEG_WAVE_PER_PACKET = 1, HAMMING_SEG_PACKET_PER_BLOCK = 2 };
-int hamming_seg_config_set(int mode);
-int hamming_seg_config_get(int *mode);
+int hamming_seg_config_set(uint32_t threads_per_packet);
+int hamming_seg_config_get(uint32_t *threads_per_packet);
 
 /*
  * Encode n_packets messages into segmented packets (the transmitter half):

@@ -96,13 +96,9 @@ _SIGNATURES.update({
     "hamming_decode_segmented": ([_vp, _u64, _vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _u64, _vp, _u64, _vp,
                                   _vp], _i32),
     "hamming_encode_segmented": ([_vp, _u64, _vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _u64, _vp], _i32),
-    "hamming_seg_config_set": ([_i32], _i32),
-    "hamming_seg_config_get": ([ctypes.POINTER(_i32)], _i32),
+    "hamming_seg_config_set": ([ctypes.c_uint32], _i32),
+    "hamming_seg_config_get": ([ctypes.POINTER(ctypes.c_uint32)], _i32),
 })
-
-HAMMING_SEG_AUTO = 0
-HAMMING_SEG_WAVE_PER_PACKET = 1
-HAMMING_SEG_PACKET_PER_BLOCK = 2
 
 _SIGNATURES.update({
     "hamming_planes_words": ([_u64, _i32], _u64),
@@ -320,12 +316,12 @@ def hamming_decode_segmented(enc_arena, enc_words: int, descs, n_packets: int, m
                                               _ptr(status), _stream(stream)), "hamming_decode_segmented")
 
 
-def hamming_seg_config_set(mode: int) -> None:
-    _check(library().hamming_seg_config_set(mode), "hamming_seg_config_set")
+def hamming_seg_config_set(threads_per_packet: int) -> None:
+    _check(library().hamming_seg_config_set(threads_per_packet), "hamming_seg_config_set")
 
 
 def hamming_seg_config_get() -> int:
-    m = ctypes.c_int()
+    m = ctypes.c_uint32()
     _check(library().hamming_seg_config_get(ctypes.byref(m)), "hamming_seg_config_get")
     return m.value
 

@@ -117,11 +117,12 @@ __device__ __forceinline__ uint32_t word_syndrome(const uint64_t* L, uint32_t o,
     return v;
 }
 
-// Barrier of the threads that decode one packet: one wave, or the workgroup.
+// Barrier of the threads that decode one packet: part of a wave or one wave
+// (the wave runs in lockstep), or the workgroup.
 template <uint32_t GROUP>
 __device__ __forceinline__ void group_sync()
 {
-    if constexpr (GROUP == 64) {
+    if constexpr (GROUP <= 64) {
         wave_sync();
     } else {
         __syncthreads();
@@ -188,9 +189,10 @@ struct SegArgs {
 };
 
 // Decode packet pk with GROUP threads (gl = 0..GROUP-1); L is the packet's LDS
-// slice and S its syndrome accumulators.  The checksum owners gl < t are all
-// in the first wave (t <= 32).  Every thread of the group takes the same
-// branches at the barriers.
+// slice and S its syndrome accumulators.  With GROUP < 64 several packets
+// share a wave, so pk, the descriptor and the layout are per-lane values and
+// wave-wide ballots are masked to the group.  Every thread of a group takes
+// the same branches at the barriers.
 template <uint32_t GROUP>
 __device__ __forceinline__ void decode_packet(const SegArgs& a, uint64_t pk, uint32_t gl, uint64_t* L, uint32_t* S)
 {
@@ -210,25 +212,31 @@ __device__ __forceinline__ void decode_packet(const SegArgs& a, uint64_t pk, uin
     const uint64_t* src = a.enc + d.enc_word_off;
     for (uint32_t w = gl; w < ew; w += GROUP) L[w] = __builtin_nontemporal_load(src + w);
     if (gl < 2) L[ew + gl] = 0;
-    if (gl < HAMMING_SEG_MAX_T) S[gl] = 0;
+    for (uint32_t i = gl; i < HAMMING_SEG_MAX_T; i += GROUP) S[i] = 0;
     group_sync<GROUP>();
 
     all_syndromes<GROUP>(L, Lo, S, gl);
-    const uint32_t my_s = gl < t ? S[gl] : 0u;
 
+    // checksum owners: thread gl takes segments gl, gl + GROUP, ...
     uint32_t st = 0;
-    if (gl < t) {
-        const uint32_t o = Lo.o(gl), n = Lo.n(gl);
-        if (my_s >= 1 && my_s <= n) {
-            const uint32_t bit = o + my_s - 1;
+    for (uint32_t i = gl; i < t; i += GROUP) {
+        const uint32_t s = S[i], o = Lo.o(i), n = Lo.n(i);
+        if (s >= 1 && s <= n) {
+            const uint32_t bit = o + s - 1;
             atomicXor(reinterpret_cast<unsigned long long*>(&L[bit >> 6]), 1ull << (bit & 63));
-            st = 1;
-        } else if (my_s > n) {
+            st = max(st, 1u);
+        } else if (s > n) {
             st = 2;
         }
-        if (a.syndromes) a.syndromes[d.seg_off + gl] = uint16_t(my_s);
+        if (a.syndromes) a.syndromes[d.seg_off + i] = uint16_t(s);
     }
-    const uint64_t any2 = __ballot(st == 2), any1 = __ballot(st == 1);
+    uint64_t mask = ~uint64_t(0);
+    if constexpr (GROUP < 64) mask = ((uint64_t(1) << GROUP) - 1) << ((threadIdx.x & 63u) & ~(GROUP - 1));
+    if constexpr (GROUP > 64) {
+        // t <= 32: every owner is in the first wave, whose ballot decides
+        mask = (threadIdx.x < 64) ? mask : 0;
+    }
+    const uint64_t any2 = __ballot(st == 2) & mask, any1 = __ballot(st == 1) & mask;
     if (a.status && gl == 0) a.status[pk] = any2 ? 2 : (any1 ? 1 : 0);
     group_sync<GROUP>();
 
@@ -269,15 +277,17 @@ __device__ __forceinline__ void decode_packet(const SegArgs& a, uint64_t pk, uin
     }
 }
 
-// Throughput form: four packets per block, one wave each.
+// Throughput form: 256 / GROUP packets per block, GROUP threads each (a
+// wave, or a part of one for short packets).
+template <uint32_t GROUP>
 __global__ __launch_bounds__(64 * kSegWaves) void seg_decode_kernel(SegArgs a)
 {
     extern __shared__ uint64_t lds[];
-    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint64_t pk = uint64_t(blockIdx.x) * kSegWaves + wib;
+    const uint32_t slot = threadIdx.x / GROUP;
+    const uint64_t pk = uint64_t(blockIdx.x) * (64 * kSegWaves / GROUP) + slot;
     if (pk >= a.n_packets) return;
-    uint64_t* L = lds + wib * (a.slice_words + kSynWords);
-    decode_packet<64>(a, pk, threadIdx.x & 63u, L, reinterpret_cast<uint32_t*>(L + a.slice_words));
+    uint64_t* L = lds + slot * (a.slice_words + kSynWords);
+    decode_packet<GROUP>(a, pk, threadIdx.x % GROUP, L, reinterpret_cast<uint32_t*>(L + a.slice_words));
 }
 
 // Latency form: one packet per block, all four waves on it.
@@ -361,10 +371,18 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_encode_kernel(SegArgs a)
     for (uint32_t w = lane; w < ew; w += 64) __builtin_nontemporal_store(E[w], dst + w);
 }
 
-// Batches up to this many packets use one workgroup per packet: fewer
-// packets than the GPU has wave slots, so shorter per-packet latency wins.
+// Threads per packet when the caller leaves the choice to the library: a
+// workgroup per packet for batches too small to fill the GPU's wave slots
+// (latency), otherwise a group sized to the packets (throughput).
 constexpr uint32_t kWideMaxPackets = 2048;
-std::atomic<int> g_seg_mode{HAMMING_SEG_AUTO};
+std::atomic<uint32_t> g_seg_threads{0};
+
+uint32_t auto_threads_per_packet(uint32_t n_packets, uint32_t max_msg_bytes)
+{
+    if (n_packets <= kWideMaxPackets) return 256;
+    // measured on the Table 1 grid: 16 threads up to 1600-byte packets, 32 at 2000
+    return max_msg_bytes <= 1664 ? 16u : (max_msg_bytes <= 3072 ? 32u : 64u);
+}
 
 int check_common(const void* enc, const void* descs, uint32_t n_packets, const void* msg, uint32_t max_msg_bytes)
 {
@@ -399,17 +417,19 @@ int64_t hamming_seg_layout(uint32_t msg_bytes, uint32_t t, uint32_t* k_out, uint
     return total;
 }
 
-int hamming_seg_config_set(int mode)
+int hamming_seg_config_set(uint32_t threads_per_packet)
 {
-    if (mode < HAMMING_SEG_AUTO || mode > HAMMING_SEG_PACKET_PER_BLOCK) return HAMMING_EINVAL;
-    g_seg_mode.store(mode);
+    if (threads_per_packet != 0 && threads_per_packet != 16 && threads_per_packet != 32 &&
+        threads_per_packet != 64 && threads_per_packet != 256)
+        return HAMMING_EINVAL;
+    g_seg_threads.store(threads_per_packet);
     return HAMMING_OK;
 }
 
-int hamming_seg_config_get(int* mode)
+int hamming_seg_config_get(uint32_t* threads_per_packet)
 {
-    if (!mode) return HAMMING_EINVAL;
-    *mode = g_seg_mode.load();
+    if (!threads_per_packet) return HAMMING_EINVAL;
+    *threads_per_packet = g_seg_threads.load();
     return HAMMING_OK;
 }
 
@@ -422,15 +442,21 @@ int hamming_decode_segmented(const uint64_t* enc_arena, uint64_t enc_words, cons
     if (syndromes && (reinterpret_cast<uintptr_t>(syndromes) & 1u)) return HAMMING_EALIGN;
     SegArgs a{enc_arena, enc_words, descs, n_packets, max_msg_bytes, msg_arena, msg_words,
               syndromes, syndromes ? syndrome_count : 0, status, enc_slice_words(max_msg_bytes)};
-    const int mode = g_seg_mode.load();
-    const bool wide = mode == HAMMING_SEG_PACKET_PER_BLOCK || (mode == HAMMING_SEG_AUTO && n_packets <= kWideMaxPackets);
-    if (wide) {
+    uint32_t group = g_seg_threads.load();
+    if (group == 0) group = auto_threads_per_packet(n_packets, max_msg_bytes);
+    if (group == 256) {
         const size_t lds = size_t(a.slice_words + kSynWords) * 8;
         hipLaunchKernelGGL(seg_decode_wide_kernel, dim3(n_packets), dim3(64 * kSegWaves), lds, stream, a);
     } else {
-        const size_t lds = size_t(kSegWaves) * (a.slice_words + kSynWords) * 8;
-        const uint32_t blocks = (n_packets + kSegWaves - 1) / kSegWaves;
-        hipLaunchKernelGGL(seg_decode_kernel, dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
+        const uint32_t per_block = 64 * kSegWaves / group;
+        const size_t lds = size_t(per_block) * (a.slice_words + kSynWords) * 8;
+        const uint32_t blocks = (n_packets + per_block - 1) / per_block;
+        if (group == 16)
+            hipLaunchKernelGGL(seg_decode_kernel<16>, dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
+        else if (group == 32)
+            hipLaunchKernelGGL(seg_decode_kernel<32>, dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
+        else
+            hipLaunchKernelGGL(seg_decode_kernel<64>, dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
     }
     return hipGetLastError() == hipSuccess ? HAMMING_OK : HAMMING_EDEVICE;
 }

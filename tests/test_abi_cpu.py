@@ -300,10 +300,10 @@ def test_host_mapped_mode_argument_checks():
 def test_segmented_mode_config_roundtrip():
     old = hm.hamming_seg_config_get()
     try:
-        for m in (hm.HAMMING_SEG_WAVE_PER_PACKET, hm.HAMMING_SEG_PACKET_PER_BLOCK, hm.HAMMING_SEG_AUTO):
+        for m in (16, 32, 64, 256, 0):
             hm.hamming_seg_config_set(m)
             assert hm.hamming_seg_config_get() == m
-        for bad in (-1, 3):
+        for bad in (1, 8, 128, 512):
             with pytest.raises(hm.HammingError):
                 hm.hamming_seg_config_set(bad)
     finally:

@@ -13,7 +13,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-MODES = [1, 2]   # one wave per packet, one workgroup per packet
+MODES = [16, 32, 64, 256]   # threads per packet
 
 
 @pytest.fixture
