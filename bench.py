@@ -43,16 +43,19 @@ DOMINANT_SOURCES = ("abi.hip", "decode_plain.hip", "hamming_device.h", "launch.h
 
 
 def kernel_source_digest() -> str:
-    """Digest of the plain decode kernel's sources and the launch shapes the
-    bench loads."""
+    """Digest of the plain decode kernel's sources and of the plain-decode
+    launch shapes the bench loads (the batched lines of the tuning cache do
+    not affect this kernel)."""
     h = hashlib.sha256()
-    files = [os.path.join(ROOT, "paper_1412_6862_amd", "csrc", f) for f in DOMINANT_SOURCES]
-    if os.path.exists(TUNED_SHAPES):
-        files.append(TUNED_SHAPES)
-    for p in files:
-        with open(p, "rb") as fh:
-            h.update(os.path.basename(p).encode())
+    for f in DOMINANT_SOURCES:
+        with open(os.path.join(ROOT, "paper_1412_6862_amd", "csrc", f), "rb") as fh:
+            h.update(f.encode())
             h.update(fh.read())
+    if os.path.exists(TUNED_SHAPES):
+        with open(TUNED_SHAPES, "rb") as fh:
+            for line in fh:
+                if line.startswith(b'{"device"') or line.startswith(b'{"plain"'):
+                    h.update(line)
     return h.hexdigest()[:16]
 
 

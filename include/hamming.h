@@ -210,7 +210,7 @@ int hamming_decode_batch(const uint64_t *cw_arena, uint64_t cw_words,
 
 /*
  * Launch shape of the batched decode (a tuning knob, no effect on results):
- * schedule selects the per-r lane widths and occupancy (0, 1 or 2); xcd_chunk (1..2^20) the
+ * schedule selects the per-r lane widths and occupancy (0..3); xcd_chunk (1..2^20) the
  * consecutive workgroups each of the 8 XCDs takes in turn (1 = hardware
  * order); grid_cap_blocks caps the decode kernel's workgroups (0 = no cap;
  * waves then loop over tiles); use_graph whether to capture and replay a

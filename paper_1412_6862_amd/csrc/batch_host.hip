@@ -15,7 +15,7 @@ namespace {
 
 using hm::BatchArgs;
 
-std::atomic<int> g_schedule{2};
+std::atomic<int> g_schedule{3};
 std::atomic<uint32_t> g_grid_cap{0};
 std::atomic<uint32_t> g_xcd_chunk{1};
 std::atomic<int> g_use_graph{1};
@@ -112,7 +112,7 @@ int hamming_batch_layout(hamming_packet* descs, uint32_t n, uint64_t* data_words
 
 int hamming_batch_config_set(int schedule, uint32_t xcd_chunk, uint32_t grid_cap_blocks, int use_graph)
 {
-    if (schedule < 0 || schedule > 2 || xcd_chunk < 1 || xcd_chunk > (1u << 20) ||
+    if (schedule < 0 || schedule > 3 || xcd_chunk < 1 || xcd_chunk > (1u << 20) ||
         (use_graph != 0 && use_graph != 1))
         return HAMMING_EINVAL;
     g_schedule.store(schedule);

@@ -44,6 +44,7 @@ struct Schedule {
 using Sched0 = Schedule<8, 8, 8, 8, 2, 4>;
 using Sched1 = Schedule<8, 4, 4, 4, 2, 6>;
 using Sched2 = Schedule<8, 4, 4, 4, 2, 8>;
+using Sched3 = Schedule<8, 8, 8, 4, 2, 8>;
 
 __device__ __forceinline__ uint64_t message_words(uint64_t n_cw, uint32_t r)
 {
@@ -248,6 +249,7 @@ hipError_t launch_batch(const BatchArgs& a, int schedule, uint32_t grid, hipStre
     case 0: return launch_batch_s<Sched0>(a, grid, stream);
     case 1: return launch_batch_s<Sched1>(a, grid, stream);
     case 2: return launch_batch_s<Sched2>(a, grid, stream);
+    case 3: return launch_batch_s<Sched3>(a, grid, stream);
     default: return hipErrorInvalidValue;
     }
 }

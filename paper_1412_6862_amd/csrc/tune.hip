@@ -174,7 +174,7 @@ int hamming_tune(const char* cache_path, uint32_t flags, hipStream_t stream)
             hipMemcpy(n_dev, &np, 4, hipMemcpyHostToDevice) != hipSuccess)
             return HAMMING_EDEVICE;
         float best = 1e30f;
-        for (int sched : {0, 1, 2}) {
+        for (int sched : {0, 1, 2, 3}) {
             for (uint32_t xc : kXcdChoices) {
                 // direct launches while tuning: no graph is cached for these scratch buffers
                 if (hamming_batch_config_set(sched, xc, 0, 0) != HAMMING_OK) return HAMMING_EINVAL;

@@ -152,7 +152,7 @@ def test_batch_config_roundtrip():
         assert hm.hamming_batch_config_get() == (1, 4, 4096, 0)
         hm.hamming_batch_config_set(2, 1, 0, 1)
         assert hm.hamming_batch_config_get() == (2, 1, 0, 1)
-        for args in ((3, 2, 8, 1), (-1, 2, 8, 1), (0, 2, 8, 2), (0, 0, 0, 1), (0, (1 << 20) + 1, 0, 1)):
+        for args in ((4, 2, 8, 1), (-1, 2, 8, 1), (0, 2, 8, 2), (0, 0, 0, 1), (0, (1 << 20) + 1, 0, 1)):
             with pytest.raises(hm.HammingError):
                 hm.hamming_batch_config_set(*args)
     finally:

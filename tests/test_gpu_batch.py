@@ -93,7 +93,7 @@ def test_batch_matches_oracle_and_leaves_gaps(gpu_device, seed):
     _check_outputs(bd, descs, expect, data_fill=0x5A, ep_fill=0xA5)
 
 
-@pytest.mark.parametrize("schedule", [0, 1, 2])
+@pytest.mark.parametrize("schedule", [0, 1, 2, 3])
 @pytest.mark.parametrize("xcd_chunk", [1, 3, 64])
 @pytest.mark.parametrize("grid_cap", [0, 1, 5])
 @pytest.mark.parametrize("use_graph", [0, 1])
