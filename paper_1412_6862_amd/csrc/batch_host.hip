@@ -171,8 +171,12 @@ int hamming_decode_batch(const uint64_t* cw_arena, uint64_t cw_words, const hamm
     const int schedule = g_schedule.load();
     // One wave per tile of the largest batch these arguments allow; a smaller
     // grid is still correct (waves loop), only slower.
-    const uint64_t tiles = (max_codewords ? max_codewords / hm::kMinTileCodewords : cw_words / hm::kMinTileWords) +
-                           uint64_t(max_packets);
+    // the input arena bounds the codewords as well as the hint does; take the
+    // tighter of the two (excess waves only read the totals and exit, but at
+    // 4x the real tile count they cost a noticeable tail)
+    uint64_t tiles = cw_words / hm::kMinTileWords;
+    if (max_codewords && max_codewords / hm::kMinTileCodewords < tiles) tiles = max_codewords / hm::kMinTileCodewords;
+    tiles += uint64_t(max_packets);
     uint64_t blocks = (tiles + hm::kWavesPerBlockHost - 1) / hm::kWavesPerBlockHost;
     const uint64_t cap = g_grid_cap.load();
     if (cap && blocks > cap) blocks = cap;

@@ -205,14 +205,21 @@ void decode_batch_kernel(
     // the table and descriptor reads below are scalar loads
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t* lds = reinterpret_cast<uint32_t*>(&lds_raw[wave][0]);
-    const uint64_t total = ws->total_tiles;
     const uint64_t waves = uint64_t(gridDim.x) * kWavesPerBlock;
     uint64_t t = uint64_t(xcd_block(blockIdx.x, gridDim.x, a.xcd_chunk)) * kWavesPerBlock + wave;
+    // Read this tile's map entry together with the batch totals instead of
+    // after them: when the map has one entry per tile (fine_log2 = 0, the
+    // usual case) it is the entry needed.  The index is clamped to the map, so
+    // the read stays in bounds whatever the totals turn out to be.
+    const uint32_t p_first = fine[t < a.fine_cap ? t : a.fine_cap - 1];
+    const uint64_t total = ws->total_tiles;
     if (t >= total) return;
     const uint32_t n = uint32_t(ws->n_packets);
     const uint32_t gf = ws->fine_log2;
+    bool first = true;
     for (; t < total; t += waves) {
-        uint32_t p = fine[t >> gf];
+        uint32_t p = (first && gf == 0) ? p_first : fine[t >> gf];
+        first = false;
         if (gf) p = probe_packet(ts, n, t, p);
         const hamming_packet d = descs[p];
         const uint64_t tl = t - ts[p];
