@@ -90,7 +90,7 @@ int hamming_tune(const char* cache_path, uint32_t flags, hipStream_t stream)
     const bool do_plain = (flags & 1u) != 0, do_batch = (flags & 2u) != 0;
     if (!do_plain && !do_batch) return HAMMING_EINVAL;
     const uint64_t n6 = uint64_t(1) << 26;              // codewords per plain trial (2^25 for r = 7)
-    DevBuf cw, data, ep, ws, descs_dev;
+    DevBuf cw, data, ep, ws, descs_dev, bcw, bdata, bep;
     hipError_t e = hipMalloc(&cw.p, n6 * 8);
     if (e == hipSuccess) e = hipMalloc(&data.p, n6 * 8);
     if (e == hipSuccess) e = hipMalloc(&ep.p, n6);
@@ -140,38 +140,53 @@ int hamming_tune(const char* cache_path, uint32_t flags, hipStream_t stream)
         batch.ms = 0;
     }
     if (do_batch) {
-        // 500 packets, sizes log-uniform in [64, 2^18] codewords, r uniform in 3..7
-        const uint32_t np = 500;
+        // a batch shaped like large production batches: 2000 packets, sizes
+        // log-uniform in [64, 2^20] codewords, r uniform in 3..7, in a 2 GiB
+        // arena (the footprint, not only the packet mix, decides the best shape)
+        const uint32_t np = 2000;
+        const uint64_t arena_words = uint64_t(1) << 28;
         std::vector<hamming_packet> d(np);
         uint64_t state = 0x6862ull, off = 0, total = 0;
         auto next = [&] {
             state = state * 6364136223846793005ull + 1442695040888963407ull;
             return double(state >> 11) / 9007199254740992.0;
         };
+        uint32_t used = 0;
         for (uint32_t i = 0; i < np; ++i) {
-            d[i].n_cw = uint64_t(64.0 * std::exp2(12.0 * next()));
-            d[i].r = 3 + uint32_t(5.0 * next()) % 5;
-            d[i].flags = 0;
-            d[i].in_word_off = off;
-            off += d[i].n_cw * (d[i].r == 7 ? 2 : 1);
-            total += d[i].n_cw;
+            hamming_packet q;
+            memset(&q, 0, sizeof q);
+            q.n_cw = uint64_t(64.0 * std::exp2(14.0 * next()));
+            q.r = 3 + uint32_t(5.0 * next()) % 5;
+            q.in_word_off = off;
+            const uint64_t words = q.n_cw * (q.r == 7 ? 2 : 1);
+            if (off + words > arena_words) break;
+            off += words;
+            total += q.n_cw;
+            d[used++] = q;
         }
+        d.resize(used);
+        const uint32_t nb = used;
         uint64_t dw = 0, eb = 0;
-        int rc = hamming_batch_layout(d.data(), np, &dw, &eb);
+        int rc = hamming_batch_layout(d.data(), nb, &dw, &eb);
         if (rc != HAMMING_OK) return rc;
-        if (off > n6 || dw > n6 || eb > n6) return HAMMING_ERANGE;
-        const uint64_t wsb = hamming_batch_workspace_bytes(np);
-        e = hipMalloc(&ws.p, wsb);
-        if (e == hipSuccess) e = hipMalloc(&descs_dev.p, np * sizeof(hamming_packet) + 8);
+        const uint64_t wsb = hamming_batch_workspace_bytes(nb);
+        e = hipMalloc(&bcw.p, arena_words * 8);
+        if (e == hipSuccess) e = hipMalloc(&bdata.p, dw * 8 + 16);
+        if (e == hipSuccess) e = hipMalloc(&bep.p, eb + 16);
+        if (e == hipSuccess) e = hipMalloc(&ws.p, wsb);
+        if (e == hipSuccess) e = hipMalloc(&descs_dev.p, nb * sizeof(hamming_packet) + 8);
         if (e != hipSuccess) {
             fprintf(stderr, "hamming_tune: device allocation failed: %s\n", hipGetErrorString(e));
             (void)hipGetLastError();
             return HAMMING_ENOMEM;
         }
+        hipLaunchKernelGGL(fill_random_kernel, dim3(8192), dim3(256), 0, stream, static_cast<uint64_t*>(bcw.p),
+                           arena_words, 0x6862ull);
+        if (hipGetLastError() != hipSuccess) return HAMMING_EDEVICE;
         uint32_t* n_dev = static_cast<uint32_t*>(descs_dev.p);
         auto* dd = reinterpret_cast<hamming_packet*>(static_cast<char*>(descs_dev.p) + 8);
-        if (hipMemcpy(dd, d.data(), np * sizeof(hamming_packet), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(n_dev, &np, 4, hipMemcpyHostToDevice) != hipSuccess)
+        if (hipMemcpy(dd, d.data(), nb * sizeof(hamming_packet), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(n_dev, &nb, 4, hipMemcpyHostToDevice) != hipSuccess)
             return HAMMING_EDEVICE;
         float best = 1e30f;
         for (int sched : {0, 1, 2, 3}) {
@@ -180,8 +195,8 @@ int hamming_tune(const char* cache_path, uint32_t flags, hipStream_t stream)
                 if (hamming_batch_config_set(sched, xc, 0, 0) != HAMMING_OK) return HAMMING_EINVAL;
                 float ms = 0;
                 rc = time_ms(stream, 2, 5, [&] {
-                    return hamming_decode_batch(static_cast<const uint64_t*>(cw.p), off, dd, n_dev, np, total,
-                                                static_cast<uint64_t*>(data.p), dw, static_cast<uint8_t*>(ep.p), eb,
+                    return hamming_decode_batch(static_cast<const uint64_t*>(bcw.p), off, dd, n_dev, nb, total,
+                                                static_cast<uint64_t*>(bdata.p), dw, static_cast<uint8_t*>(bep.p), eb,
                                                 nullptr, ws.p, wsb, stream);
                 }, &ms);
                 if (rc != HAMMING_OK) return rc;
