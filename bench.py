@@ -284,7 +284,8 @@ def serving_leg(dev, plain_gBps_per_r: dict, loads, n_requests: int, warm: int):
 
 def latency_leg(dev, reps: int):
     """Hamming(7,4), one packet of 65,536 codewords (p = 0.5): a latency-bound
-    launch; p50/p99 of single-launch time over `reps` launches."""
+    launch; p50/p99 of single-launch time over `reps` launches, beside the
+    same measurement of a one-element torch kernel (the launch floor)."""
     import numpy as np
     import torch
 
@@ -295,12 +296,14 @@ def latency_leg(dev, reps: int):
     data = torch.empty(hm.hamming_data_bytes(n, r), dtype=torch.uint8, device=dev)
     ep = torch.empty(n, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
-    t = time_events(lambda: hm.hamming_decode(cw, n, r, data, ep, stream), stream, 20, reps)
-    t = np.array(t) * 1e3
+    t = np.array(time_events(lambda: hm.hamming_decode(cw, n, r, data, ep, stream), stream, 20, reps)) * 1e3
+    one = torch.zeros(1, dtype=torch.int32, device=dev)
+    f = np.array(time_events(lambda: one.add_(1), stream, 20, reps)) * 1e3
     return {"workload": "Hamming(7,4), one packet of 65,536 codewords, 50% single-bit errors",
             "launches": reps, "p50_us": round(float(np.percentile(t, 50)), 2),
             "p99_us": round(float(np.percentile(t, 99)), 2),
-            "payload_Gbps_at_p50": round(n * 4 / float(np.percentile(t, 50)) / 1e3, 1)}
+            "payload_Gbps_at_p50": round(n * 4 / float(np.percentile(t, 50)) / 1e3, 1),
+            "launch_floor_p50_us": round(float(np.percentile(f, 50)), 2)}
 
 
 def hamming127_leg(dev, reps: int):
