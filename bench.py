@@ -189,6 +189,17 @@ def batched_leg(dev, n_packets: int, reps: int):
         for rr, (cw, total) in per_r.items():
             tp = time_events(lambda: hm.hamming_decode(cw, total, rr, data, ep, stream), stream, 2, reps)
             plain_ms += tp[len(tp) // 2]
+    # the naive alternative: one plain launch per packet, same arenas
+    lib = hm.library()
+    base_in, base_out, base_ep = arena.data_ptr(), bd.data.data_ptr(), bd.errpos.data_ptr()
+    calls = [(base_in + 8 * int(d["in_word_off"]), int(d["n_cw"]), int(d["r"]), base_out + 8 * int(d["data_word_off"]),
+              base_ep + int(d["errpos_off"])) for d in descs]
+    sh = stream.cuda_stream
+    with torch.cuda.stream(stream):
+        def naive():
+            for c in calls:
+                lib.hamming_decode(c[0], c[1], c[2], c[3], c[4], sh)
+        t_naive = time_events(naive, stream, 1, 2)
     k = (1 << r) - 1 - r
     bits = float((n_cw * k).sum())
     algo = float(sum(n_cw[r == rr].sum() * algorithmic_bytes_per_codeword(rr) for rr in range(3, 8)))
@@ -205,6 +216,7 @@ def batched_leg(dev, n_packets: int, reps: int):
         "frac_hbm": round(algo / med / 1e6 / HBM_PEAK_GBPS, 4),
         "plain_same_mix_ms": round(plain_ms, 3),
         "batched_over_plain": round(plain_ms / med, 4),
+        "naive_one_launch_per_packet_ms": round(t_naive[0], 2),
         "schedule": list(hm.hamming_batch_config_get()),
     }
 
@@ -415,7 +427,8 @@ def sizes_leg(dev):
             algo = algorithmic_bytes_per_codeword(r) * n
             rows.append({"r": r, "n_cw": n, "us_p50": round(med * 1e3, 2),
                          "payload_Gbps": round(n * k / med / 1e6, 1),
-                         "frac_hbm": round(algo / med / 1e6 / HBM_PEAK_GBPS, 4)})
+                         "frac_hbm": round(algo / med / 1e6 / HBM_PEAK_GBPS, 4),
+                         "cache_resident": algo < 256e6})
         del cw, data, ep
         torch.cuda.empty_cache()
     return {"workload": "plain decode, packet sizes 2^10..2^28 codewords (every 4x) of r = 4, 5, 6, "
@@ -534,6 +547,21 @@ def cpu_segmented(n_packets: int):
     return out
 
 
+def copy_ceiling(dev) -> float:
+    """Device-to-device copy of 1 GiB through the runtime (read + write bytes
+    per second), the reference point for a kernel that reads and writes HBM
+    once each."""
+    import torch
+
+    src = torch.ones(1 << 27, dtype=torch.int64, device=dev)
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    t = time_events(lambda: dst.copy_(src), stream, 3, 10)
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(2 * (1 << 30) / t[len(t) // 2] / 1e6, 1)
+
+
 def cpu_baseline(log2_sample: int):
     """The oracle on the host cores over a slice of the same workload."""
     import oracle
@@ -553,6 +581,21 @@ def cpu_baseline(log2_sample: int):
         oracle.decode(y, r, nthreads=threads)
         elapsed += time.perf_counter() - t0
         bits += n * ((1 << r) - 1 - r)
+        if r == WORKLOAD_R[-1]:
+            # one thread on a 2^22 slice of the same packet: the analogue of a sequential decoder
+            m = min(n, 1 << 22)
+            t0 = time.perf_counter()
+            oracle.decode(y[:m], r, nthreads=1)
+            single = m * ((1 << r) - 1 - r) / (time.perf_counter() - t0) / 1e9
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": round(bits / elapsed / 1e9, 3),
         "unit": "Gbit/s",
@@ -560,6 +603,9 @@ def cpu_baseline(log2_sample: int):
         "kind": "oracle",
         "sample": "2^%d codewords of each of r=4,5,6 (p=%.2f), %d threads, decode only, %.2f s"
                   % (log2_sample, P_SINGLE, threads, elapsed),
+        "single_thread_Gbps_r6": round(single, 3),
+        "cpu_model": model,
+        "host_cpus": os.cpu_count(),
         "segmented_us_per_packet_1thread": cpu_segmented(100),
     }
 
@@ -698,6 +744,7 @@ def main() -> int:
             "traffic": traffic,
             "algorithmic_bytes_per_launch": int(algorithmic_bytes_per_codeword(DOMINANT_R) * n_cw),
             "avg_launch_us": dom["avg_us"],
+            "runtime_d2d_copy_GBps": copy_ceiling(dev),
         },
         "per_r": per_r,
         "tuned_shapes": tuned,
@@ -715,7 +762,7 @@ def main() -> int:
     if "serve" in legs:
         gBps = {x["r"]: x["algorithmic_GBps"] for x in per_r}
         gBps.setdefault(7, gBps[DOMINANT_R])
-        out["serving"] = serving_leg(dev, gBps, (0.1, 0.3, 0.5, 0.7, 0.9), args.serve_requests,
+        out["serving"] = serving_leg(dev, gBps, (0.1, 0.3, 0.5, 0.7, 0.8, 0.9), args.serve_requests,
                                      max(200, args.serve_requests // 10))
     if "host" in legs:
         out["host_pipeline"] = host_leg(dev, 3)
@@ -725,6 +772,10 @@ def main() -> int:
         out["segmented"] = segmented_leg(dev, args.seg_packets, 5, 200)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_log2)
+        cb = out["cpu_baseline"]
+        cb["gpu_over_oracle"] = {
+            "all_threads": round(out["value"] / cb["value"], 0),
+            "single_thread_r6": round(dom["payload_Gbps"] / cb["single_thread_Gbps_r6"], 0)}
         if "segmented" in out:
             cpu = out["cpu_baseline"]["segmented_us_per_packet_1thread"]
             for row in out["segmented"]["shapes"]:
