@@ -28,10 +28,12 @@ constexpr uint32_t kSegWaves = 4;                          // packets per block
 constexpr uint32_t kSynWords = HAMMING_SEG_MAX_T / 2;      // per-wave syndrome accumulators, in 64-bit words
 
 // Longest encoded packet of at most max_msg_bytes message bytes, in 64-bit
-// words, plus two zero words that unaligned two-word reads may touch.
+// words, plus a zero word in front (so the word holding positions 0..63 of the
+// first segment reads as any other) and two behind (that unaligned two-word
+// reads may touch).
 __host__ __device__ inline uint32_t enc_slice_words(uint32_t max_msg_bytes)
 {
-    return (8u * max_msg_bytes + 16u * HAMMING_SEG_MAX_T + 63u) / 64u + 2u;
+    return (8u * max_msg_bytes + 16u * HAMMING_SEG_MAX_T + 63u) / 64u + 3u;
 }
 
 __host__ __device__ inline uint32_t msg_slice_words(uint32_t max_msg_bytes)
@@ -39,19 +41,22 @@ __host__ __device__ inline uint32_t msg_slice_words(uint32_t max_msg_bytes)
     return (max_msg_bytes + 7u) / 8u + 2u;
 }
 
-// Checksum bits of a shortened segment with k message bits: the smallest r
-// with 2^r - 1 - r >= k.
+// Checksum bits of a shortened segment with k >= 1 message bits: the
+// smallest r >= 2 with 2^r - 1 - r >= k.  With b the bit length of k, r is b,
+// or b + 1 when 2^b - 1 - b < k (2^(b-1) - b < k always rules out b - 1).
 __host__ __device__ inline uint32_t seg_checksum_bits(uint32_t k)
 {
-    uint32_t r = 2;
-    while ((1u << r) - 1u - r < k) ++r;
-    return r;
+    const uint32_t b = 32u - uint32_t(__builtin_clz(k));
+    const uint32_t r = b + (((1u << b) - 1u - b) < k ? 1u : 0u);
+    return r < 2 ? 2 : r;
 }
 
+// 64 bits starting at an arbitrary bit of an LDS word array (both words read,
+// no branch: the high word is shifted in two steps so a shift of 0 is defined).
 __device__ __forceinline__ uint64_t read_bits64(const uint64_t* L, uint64_t bit)
 {
     const uint32_t q = uint32_t(bit >> 6), sh = uint32_t(bit & 63);
-    return sh ? (L[q] >> sh) | (L[q + 1] << (64 - sh)) : L[q];
+    return (L[q] >> sh) | ((L[q + 1] << 1) << (63 - sh));
 }
 
 // Segment layout of one packet in closed form.  The first `rem` segments
@@ -102,7 +107,9 @@ __device__ __forceinline__ bool make_layout(uint32_t msg_bytes, uint32_t t, uint
 // of q, so those five parities are taken on the XOR of the two halves.
 __device__ __forceinline__ uint32_t word_syndrome(const uint64_t* L, uint32_t o, uint32_t n, uint32_t w)
 {
-    uint64_t x = (o == 0 && w == 0) ? (L[0] << 1) : read_bits64(L, uint64_t(o) + 64u * w - 1u);
+    // position 64w + q is bit o + 64w + q - 1 of L, read from the zero word in
+    // front of L for o = w = 0
+    uint64_t x = read_bits64(L - 1, uint64_t(o) + 64u * w + 63u);
     if (w == 0) x &= ~uint64_t(1);                     // there is no position 0
     const uint32_t hi = n - 64u * w;                    // last valid bit index in this word
     if (hi < 63) x &= (uint64_t(2) << hi) - 1;
@@ -145,8 +152,7 @@ __device__ __forceinline__ void all_syndromes(const uint64_t* L, const Layout& L
             ++i;
             nw = i < Lo.rem ? Lo.nwA : Lo.nwB;
         }
-        const uint32_t v = word_syndrome(L, Lo.o(i), Lo.n(i), w);
-        if (v) atomicXor(&S[i], v);
+        atomicXor(&S[i], word_syndrome(L, Lo.o(i), Lo.n(i), w));
         w += GROUP;
     }
     group_sync<GROUP>();
@@ -211,7 +217,7 @@ __device__ __forceinline__ void decode_packet(const SegArgs& a, uint64_t pk, uin
 
     const uint64_t* src = a.enc + d.enc_word_off;
     for (uint32_t w = gl; w < ew; w += GROUP) L[w] = __builtin_nontemporal_load(src + w);
-    if (gl < 2) L[ew + gl] = 0;
+    if (gl < 3) L[gl == 2 ? -1 : int64_t(ew + gl)] = 0;
     for (uint32_t i = gl; i < HAMMING_SEG_MAX_T; i += GROUP) S[i] = 0;
     group_sync<GROUP>();
 
@@ -286,8 +292,8 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_decode_kernel(SegArgs a)
     const uint32_t slot = threadIdx.x / GROUP;
     const uint64_t pk = uint64_t(blockIdx.x) * (64 * kSegWaves / GROUP) + slot;
     if (pk >= a.n_packets) return;
-    uint64_t* L = lds + slot * (a.slice_words + kSynWords);
-    decode_packet<GROUP>(a, pk, threadIdx.x % GROUP, L, reinterpret_cast<uint32_t*>(L + a.slice_words));
+    uint64_t* slice = lds + slot * (a.slice_words + kSynWords);
+    decode_packet<GROUP>(a, pk, threadIdx.x % GROUP, slice + 1, reinterpret_cast<uint32_t*>(slice + a.slice_words));
 }
 
 // Latency form: one packet per block, all four waves on it.
@@ -296,7 +302,7 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_decode_wide_kernel(SegArgs
     extern __shared__ uint64_t lds[];
     const uint64_t pk = blockIdx.x;
     if (pk >= a.n_packets) return;
-    decode_packet<64 * kSegWaves>(a, pk, threadIdx.x, lds, reinterpret_cast<uint32_t*>(lds + a.slice_words));
+    decode_packet<64 * kSegWaves>(a, pk, threadIdx.x, lds + 1, reinterpret_cast<uint32_t*>(lds + a.slice_words));
 }
 
 __global__ __launch_bounds__(64 * kSegWaves) void seg_encode_kernel(SegArgs a)
@@ -306,8 +312,9 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_encode_kernel(SegArgs a)
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t pk = uint64_t(blockIdx.x) * kSegWaves + wib;
     if (pk >= a.n_packets) return;
-    uint64_t* E = lds + wib * (a.slice_words + kSynWords);     // encoded words, then the message words
-    uint32_t* S = reinterpret_cast<uint32_t*>(E + a.slice_words);
+    uint64_t* slice = lds + wib * (a.slice_words + kSynWords);  // zero word, encoded words, message words
+    uint64_t* E = slice + 1;
+    uint32_t* S = reinterpret_cast<uint32_t*>(slice + a.slice_words);
 
     const hamming_seg_packet d = a.descs[pk];
     const uint32_t M = d.msg_bytes, t = d.t;
@@ -317,13 +324,14 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_encode_kernel(SegArgs a)
     const bool ok = shape_ok && d.enc_word_off <= a.enc_words && ew <= a.enc_words - d.enc_word_off &&
                     d.msg_word_off <= a.msg_words && mw <= a.msg_words - d.msg_word_off;
     if (!ok) return;
-    uint64_t* Mw = E + enc_slice_words(a.max_msg_bytes);
+    uint64_t* Mw = slice + enc_slice_words(a.max_msg_bytes);
     const uint64_t* src = a.msg + d.msg_word_off;
     for (uint32_t w = lane; w < mw; w += 64) Mw[w] = src[w];
     if (lane < 2) {
         Mw[mw + lane] = 0;
         E[ew + lane] = 0;
     }
+    if (lane == 2) E[-1] = 0;
     if (lane < HAMMING_SEG_MAX_T) S[lane] = 0;
     wave_sync();
 
