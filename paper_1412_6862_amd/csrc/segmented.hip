@@ -171,13 +171,14 @@ __device__ __forceinline__ uint64_t head_message(uint64_t w)
 
 // Run of message positions containing message bit mu >= 57 of a segment:
 // the positions strictly between 2^j and 2^(j+1) carry message bits
-// mu = p - j - 2.  Returns j (at least 6).
+// mu = p - j - 2, so j is floor(log2(mu + 2)) or one more (one comparison
+// with the next run's first message bit decides).  Returns j (at least 6;
+// callers with mu < 57 ignore it).
 __device__ __forceinline__ uint32_t run_of(uint32_t mu)
 {
-    uint32_t j = 31u - __clz(mu + 2u);
-    if (j < 6) j = 6;
-    while ((2u << j) - j - 2u <= mu) ++j;
-    return j;
+    const uint32_t j0 = 31u - __clz(mu + 2u);
+    const uint32_t j = j0 + (((2u << j0) - j0 - 2u) <= mu ? 1u : 0u);
+    return j < 6 ? 6 : j;
 }
 
 struct SegArgs {
@@ -264,16 +265,14 @@ __device__ __forceinline__ void decode_packet(const SegArgs& a, uint64_t pk, uin
                 R = Lo.o(i) - K;
                 continue;
             }
-            uint64_t v;
-            uint32_t lim;
-            if (mu < kHeadBits) {
-                v = head_message(read_bits64(L, uint64_t(K) + R)) >> mu;
-                lim = kHeadBits;
-            } else {
-                const uint32_t j = run_of(mu);
-                v = read_bits64(L, uint64_t(m) + R + j + 1);
-                lim = (2u << j) - j - 2u;
-            }
+            // one piece: the head compaction, or a run of positions; both
+            // computed with selects so that lanes in different cases do not
+            // split the wave
+            const bool head = mu < kHeadBits;
+            const uint32_t j = run_of(mu);
+            uint64_t v = read_bits64(L, head ? uint64_t(K) + R : uint64_t(m) + R + j + 1);
+            v = head ? head_message(v) >> mu : v;
+            const uint32_t lim = head ? kHeadBits : (2u << j) - j - 2u;
             const uint32_t len = min(min(lim, k) - mu, end - m);
             if (len < 64) v &= (uint64_t(1) << len) - 1;
             acc |= v << (m - 64u * ow);
