@@ -5,13 +5,15 @@
 // segment is the XOR over its index sets (Sec. III.A, III.C, Algorithm 1),
 // computed here one 64-position word at a time and reduced across the wave.
 //
-// One wave per packet: the encoded packet is staged in the wave's slice of
-// LDS, the position words of all segments are dealt to the lanes and their
-// syndrome contributions XORed into per-segment LDS accumulators, the
-// corrections are LDS atomics, and each lane then assembles whole 64-bit words
-// of the merged message from the runs of message positions between checksum
-// positions.  Segment offsets are closed-form (message sizes take two
-// values), so no lookup table is read.
+// A group of threads per packet (part of a wave, a wave or a workgroup): the
+// 64-position words of all segments are dealt to the threads and read from
+// HBM once, as unaligned two-word windows.  Each word is folded into the
+// thread's partial syndrome of its segment and its message bits (one run of
+// consecutive message indices per word) are ORed into the packet's message
+// buffer in LDS; the segment owners then finish the syndromes, flip the one
+// message bit a correctable error hits, and the buffer is stored.  Segment
+// offsets are closed-form (message sizes take two values), so no lookup
+// table is read.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -161,24 +163,132 @@ __device__ __forceinline__ void all_syndromes(const uint64_t* L, const Layout& L
 // The message positions below 64 (3, 5..7, 9..15, 17..31, 33..63) carry a
 // segment's first 57 message bits; given positions 1..64 as bits 0..63 of w,
 // this compacts them with constant masks and shifts.
-constexpr uint32_t kHeadBits = 57;
-
 __device__ __forceinline__ uint64_t head_message(uint64_t w)
 {
     return ((w >> 2) & 0x1ull) | (((w >> 4) & 0x7ull) << 1) | (((w >> 8) & 0x7Full) << 4) |
            (((w >> 16) & 0x7FFFull) << 11) | (((w >> 32) & 0x7FFFFFFFull) << 26);
 }
 
-// Run of message positions containing message bit mu >= 57 of a segment:
-// the positions strictly between 2^j and 2^(j+1) carry message bits
-// mu = p - j - 2, so j is floor(log2(mu + 2)) or one more (one comparison
-// with the next run's first message bit decides).  Returns j (at least 6;
-// callers with mu < 57 ignore it).
-__device__ __forceinline__ uint32_t run_of(uint32_t mu)
+// Syndrome of a segment from the XOR of its position words (X) and the XOR of
+// 64w over its words of odd weight (H): bits 0..4 of a position are those of
+// its bit q in the word, and q and q+32 share them, so those five parities are
+// taken on the XOR of the halves; bit 5 is the parity of the high half.
+__device__ __forceinline__ uint32_t fold_syndrome(uint64_t x, uint32_t h)
 {
-    const uint32_t j0 = 31u - __clz(mu + 2u);
-    const uint32_t j = j0 + (((2u << j0) - j0 - 2u) <= mu ? 1u : 0u);
-    return j < 6 ? 6 : j;
+    const uint32_t hi = uint32_t(x >> 32), f = uint32_t(x) ^ hi;
+    uint32_t v = h;
+    v ^= __popc(f & 0xAAAAAAAAu) & 1u;
+    v ^= (__popc(f & 0xCCCCCCCCu) & 1u) << 1;
+    v ^= (__popc(f & 0xF0F0F0F0u) & 1u) << 2;
+    v ^= (__popc(f & 0xFF00FF00u) & 1u) << 3;
+    v ^= (__popc(f & 0xFFFF0000u) & 1u) << 4;
+    v ^= (__popc(hi) & 1u) << 5;
+    return v;
+}
+
+constexpr uint32_t kBatch = 4;    // position words a thread loads before it uses them
+
+// Adds a thread's partial syndrome of segment i to the segment's accumulators.
+// Threads whose words cancelled (or that had none) skip the LDS atomics, which
+// all threads of a segment aim at the same two addresses.
+__device__ __forceinline__ void flush_partial(uint64_t* X, uint32_t* H, uint32_t i, uint64_t x, uint32_t h)
+{
+    if (x | h) {
+        atomicXor(reinterpret_cast<unsigned long long*>(&X[i]), x);
+        atomicXor(&H[i], h);
+    }
+}
+
+// One pass over the position words of every segment of a packet (thread gl
+// takes flat words gl, gl + GROUP, ...), read from HBM as two-word windows.
+// Each word is folded into the thread's partial syndrome of its segment
+// (flushed to X/H in LDS when the thread moves on to the next segment) and
+// its message positions are ORed into the message buffer Mb: for w >= 1 the
+// positions 64w+1..64w+63 of a word are all message positions and so is 64w
+// unless w is a power of two, so a word holds one run of consecutive message
+// bits whose first index is closed-form; word 0 holds the 57 head bits.
+// Mb, X and H must be zero and visible on entry; the result is visible to the
+// group on return.
+template <uint32_t GROUP>
+__device__ __forceinline__ void scan_packet(const uint64_t* src, uint32_t ew, const Layout& Lo, uint64_t* Mb,
+                                            uint64_t* X, uint32_t* H, uint32_t gl)
+{
+    const uint32_t words = Lo.syndrome_words();
+    // walk state of the next word to load: segment, word, words in the
+    // segment, first stream bit, positions, first message bit
+    uint32_t wi = 0, ww = gl, wnw = Lo.rem > 0 ? Lo.nwA : Lo.nwB, wo = 0, wn = Lo.n(0), wK = 0;
+    uint32_t ci = 0;              // segment of the partial syndrome in xacc/hacc
+    uint64_t xacc = 0;
+    uint32_t hacc = 0;
+    for (uint32_t g0 = gl; g0 < words; g0 += kBatch * GROUP) {
+        uint64_t lo[kBatch], hi[kBatch];
+        uint32_t qa[kBatch], qb[kBatch], seg[kBatch], wd[kBatch], sh[kBatch], nn[kBatch], kk[kBatch];
+#pragma unroll
+        for (uint32_t u = 0; u < kBatch; ++u) {
+            // (a slot past the packet's last word stays in the last segment;
+            // it is never used)
+            while (ww >= wnw && wi + 1 < Lo.t) {
+                ww -= wnw;
+                ++wi;
+                wnw = wi < Lo.rem ? Lo.nwA : Lo.nwB;
+                wo = Lo.o(wi);
+                wn = Lo.n(wi);
+                wK = Lo.K(wi);
+            }
+            // position 64ww of segment wi is stream bit s0 (-1, before the
+            // packet, for the first word of segment 0).  The loads are
+            // unconditional, clamped into the packet: for s0 = -1 the stray
+            // bit lands on position 0, and a word past the packet supplies
+            // only positions past the last segment; both are masked below
+            // (slots past the end are never used).
+            const int32_t s0 = int32_t(wo + 64u * ww) - 1;
+            const int32_t q = s0 >> 6;
+            qa[u] = min(uint32_t(max(q, 0)), ew - 1u);
+            qb[u] = min(uint32_t(q + 1), ew - 1u);
+            seg[u] = wi;
+            wd[u] = ww;
+            sh[u] = uint32_t(s0) & 63u;
+            nn[u] = wn;
+            kk[u] = wK;
+            ww += GROUP;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kBatch; ++u) {
+            lo[u] = src[qa[u]];
+            hi[u] = src[qb[u]];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kBatch; ++u) {
+            if (g0 + u * GROUP >= words) break;
+            const uint32_t w = wd[u], s = sh[u];
+            uint64_t x = (lo[u] >> s) | ((hi[u] << 1) << (63u - s));
+            // positions past the segment's last one, and position 0
+            const uint32_t top = min(nn[u] - 64u * w, 63u);
+            x &= (~uint64_t(0) >> (63u - top)) & ~uint64_t(w == 0 ? 1u : 0u);
+
+            if (seg[u] != ci) {
+                flush_partial(X, H, ci, xacc, hacc);
+                ci = seg[u];
+                xacc = 0;
+                hacc = 0;
+            }
+            xacc ^= x;
+            hacc ^= (__popcll(x) & 1u) ? 64u * w : 0u;
+
+            // message bits of the word and the index of the first one (pw:
+            // position 64w is a checksum position, as for w = 0 none is)
+            const uint32_t lw = 31u - __clz(w | 1u);
+            const uint32_t pw = (w & (w - 1u)) == 0u ? 1u : 0u;
+            uint64_t c = x >> pw;
+            if (w == 0) c = head_message(c);
+            const uint32_t b = kk[u] + (w == 0 ? 0u : 64u * w + pw - lw - 8u);
+            const uint32_t bq = b >> 6, bs = b & 63u;
+            atomicOr(reinterpret_cast<unsigned long long*>(&Mb[bq]), c << bs);
+            atomicOr(reinterpret_cast<unsigned long long*>(&Mb[bq + 1]), (c >> 1) >> (63u - bs));
+        }
+    }
+    flush_partial(X, H, ci, xacc, hacc);
+    group_sync<GROUP>();
 }
 
 struct SegArgs {
@@ -192,16 +302,20 @@ struct SegArgs {
     uint16_t* syndromes;
     uint64_t syndrome_count;
     uint8_t* status;
-    uint32_t slice_words;      // per-wave LDS slice (syndrome accumulators excluded)
+    uint32_t slice_words;      // per-packet LDS slice (accumulators excluded)
 };
 
-// Decode packet pk with GROUP threads (gl = 0..GROUP-1); L is the packet's LDS
-// slice and S its syndrome accumulators.  With GROUP < 64 several packets
-// share a wave, so pk, the descriptor and the layout are per-lane values and
-// wave-wide ballots are masked to the group.  Every thread of a group takes
-// the same branches at the barriers.
+// Per-packet decode accumulators after the message buffer: X, one 64-bit
+// word per segment, then H, one 32-bit word per segment.
+constexpr uint32_t kAccWords = HAMMING_SEG_MAX_T + HAMMING_SEG_MAX_T / 2;
+
+// Decode packet pk with GROUP threads (gl = 0..GROUP-1); Mb is the packet's
+// message buffer in LDS (at least mw + 1 words) and acc its accumulators.
+// With GROUP < 64 several packets share a wave, so pk, the descriptor and the
+// layout are per-lane values and wave-wide ballots are masked to the group.
+// Every thread of a group takes the same branches at the barriers.
 template <uint32_t GROUP>
-__device__ __forceinline__ void decode_packet(const SegArgs& a, uint64_t pk, uint32_t gl, uint64_t* L, uint32_t* S)
+__device__ __forceinline__ void decode_packet(const SegArgs& a, uint64_t pk, uint32_t gl, uint64_t* Mb, uint64_t* acc)
 {
     const hamming_seg_packet d = a.descs[pk];
     const uint32_t M = d.msg_bytes, t = d.t;
@@ -215,22 +329,28 @@ __device__ __forceinline__ void decode_packet(const SegArgs& a, uint64_t pk, uin
         if (a.status && gl == 0) a.status[pk] = HAMMING_SEG_INVALID;
         return;
     }
-
-    const uint64_t* src = a.enc + d.enc_word_off;
-    for (uint32_t w = gl; w < ew; w += GROUP) L[w] = __builtin_nontemporal_load(src + w);
-    if (gl < 3) L[gl == 2 ? -1 : int64_t(ew + gl)] = 0;
-    for (uint32_t i = gl; i < HAMMING_SEG_MAX_T; i += GROUP) S[i] = 0;
+    uint64_t* X = acc;
+    uint32_t* H = reinterpret_cast<uint32_t*>(acc + HAMMING_SEG_MAX_T);
+    for (uint32_t w = gl; w <= mw; w += GROUP) Mb[w] = 0;
+    for (uint32_t i = gl; i < t; i += GROUP) {
+        X[i] = 0;
+        H[i] = 0;
+    }
     group_sync<GROUP>();
 
-    all_syndromes<GROUP>(L, Lo, S, gl);
+    scan_packet<GROUP>(a.enc + d.enc_word_off, uint32_t(ew), Lo, Mb, X, H, gl);
 
-    // checksum owners: thread gl takes segments gl, gl + GROUP, ...
+    // checksum owners: thread gl takes segments gl, gl + GROUP, ...; an error
+    // at a message position flips that message bit, one at a checksum
+    // position changes no message bit
     uint32_t st = 0;
     for (uint32_t i = gl; i < t; i += GROUP) {
-        const uint32_t s = S[i], o = Lo.o(i), n = Lo.n(i);
+        const uint32_t s = fold_syndrome(X[i], H[i]), n = Lo.n(i);
         if (s >= 1 && s <= n) {
-            const uint32_t bit = o + s - 1;
-            atomicXor(reinterpret_cast<unsigned long long*>(&L[bit >> 6]), 1ull << (bit & 63));
+            if (s & (s - 1u)) {
+                const uint32_t bit = Lo.K(i) + s - (31u - __clz(s)) - 2u;
+                atomicXor(reinterpret_cast<unsigned long long*>(&Mb[bit >> 6]), 1ull << (bit & 63));
+            }
             st = max(st, 1u);
         } else if (s > n) {
             st = 2;
@@ -247,39 +367,8 @@ __device__ __forceinline__ void decode_packet(const SegArgs& a, uint64_t pk, uin
     if (a.status && gl == 0) a.status[pk] = any2 ? 2 : (any1 ? 1 : 0);
     group_sync<GROUP>();
 
-    // merge: thread-owned 64-bit words of the packet's message
-    const uint32_t nbits = 8u * M;
     uint64_t* dst = a.msg + d.msg_word_off;
-    uint32_t i = Lo.seg_of_msg(64u * gl);
-    uint32_t K = Lo.K(i), k = Lo.k(i), R = Lo.o(i) - K;       // R: checksum bits before segment i
-    for (uint32_t ow = gl; ow < mw; ow += GROUP) {
-        uint32_t m = 64u * ow;
-        const uint32_t end = min(m + 64u, nbits);
-        uint64_t acc = 0;
-        while (m < end) {
-            const uint32_t mu = m - K;
-            if (mu >= k) {
-                ++i;
-                K += k;
-                k = Lo.k(i);
-                R = Lo.o(i) - K;
-                continue;
-            }
-            // one piece: the head compaction, or a run of positions; both
-            // computed with selects so that lanes in different cases do not
-            // split the wave
-            const bool head = mu < kHeadBits;
-            const uint32_t j = run_of(mu);
-            uint64_t v = read_bits64(L, head ? uint64_t(K) + R : uint64_t(m) + R + j + 1);
-            v = head ? head_message(v) >> mu : v;
-            const uint32_t lim = head ? kHeadBits : (2u << j) - j - 2u;
-            const uint32_t len = min(min(lim, k) - mu, end - m);
-            if (len < 64) v &= (uint64_t(1) << len) - 1;
-            acc |= v << (m - 64u * ow);
-            m += len;
-        }
-        __builtin_nontemporal_store(acc, dst + ow);
-    }
+    for (uint32_t ow = gl; ow < mw; ow += GROUP) __builtin_nontemporal_store(Mb[ow], dst + ow);
 }
 
 // Throughput form: 256 / GROUP packets per block, GROUP threads each (a
@@ -291,8 +380,8 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_decode_kernel(SegArgs a)
     const uint32_t slot = threadIdx.x / GROUP;
     const uint64_t pk = uint64_t(blockIdx.x) * (64 * kSegWaves / GROUP) + slot;
     if (pk >= a.n_packets) return;
-    uint64_t* slice = lds + slot * (a.slice_words + kSynWords);
-    decode_packet<GROUP>(a, pk, threadIdx.x % GROUP, slice + 1, reinterpret_cast<uint32_t*>(slice + a.slice_words));
+    uint64_t* slice = lds + slot * (a.slice_words + kAccWords);
+    decode_packet<GROUP>(a, pk, threadIdx.x % GROUP, slice, slice + a.slice_words);
 }
 
 // Latency form: one packet per block, all four waves on it.
@@ -301,7 +390,7 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_decode_wide_kernel(SegArgs
     extern __shared__ uint64_t lds[];
     const uint64_t pk = blockIdx.x;
     if (pk >= a.n_packets) return;
-    decode_packet<64 * kSegWaves>(a, pk, threadIdx.x, lds + 1, reinterpret_cast<uint32_t*>(lds + a.slice_words));
+    decode_packet<64 * kSegWaves>(a, pk, threadIdx.x, lds, lds + a.slice_words);
 }
 
 __global__ __launch_bounds__(64 * kSegWaves) void seg_encode_kernel(SegArgs a)
@@ -387,8 +476,9 @@ std::atomic<uint32_t> g_seg_threads{0};
 uint32_t auto_threads_per_packet(uint32_t n_packets, uint32_t max_msg_bytes)
 {
     if (n_packets <= kWideMaxPackets) return 256;
-    // measured on the Table 1 grid: 16 threads up to 1600-byte packets, 32 at 2000
-    return max_msg_bytes <= 1664 ? 16u : (max_msg_bytes <= 3072 ? 32u : 64u);
+    // measured on the Table 1 grid (400..2000-byte packets): 16 threads per
+    // packet beat 32 and 64 at every size
+    return max_msg_bytes <= 2048 ? 16u : (max_msg_bytes <= 3072 ? 32u : 64u);
 }
 
 int check_common(const void* enc, const void* descs, uint32_t n_packets, const void* msg, uint32_t max_msg_bytes)
@@ -448,15 +538,15 @@ int hamming_decode_segmented(const uint64_t* enc_arena, uint64_t enc_words, cons
     if (rc != HAMMING_OK || n_packets == 0) return rc;
     if (syndromes && (reinterpret_cast<uintptr_t>(syndromes) & 1u)) return HAMMING_EALIGN;
     SegArgs a{enc_arena, enc_words, descs, n_packets, max_msg_bytes, msg_arena, msg_words,
-              syndromes, syndromes ? syndrome_count : 0, status, enc_slice_words(max_msg_bytes)};
+              syndromes, syndromes ? syndrome_count : 0, status, msg_slice_words(max_msg_bytes)};
     uint32_t group = g_seg_threads.load();
     if (group == 0) group = auto_threads_per_packet(n_packets, max_msg_bytes);
     if (group == 256) {
-        const size_t lds = size_t(a.slice_words + kSynWords) * 8;
+        const size_t lds = size_t(a.slice_words + kAccWords) * 8;
         hipLaunchKernelGGL(seg_decode_wide_kernel, dim3(n_packets), dim3(64 * kSegWaves), lds, stream, a);
     } else {
         const uint32_t per_block = 64 * kSegWaves / group;
-        const size_t lds = size_t(per_block) * (a.slice_words + kSynWords) * 8;
+        const size_t lds = size_t(per_block) * (a.slice_words + kAccWords) * 8;
         const uint32_t blocks = (n_packets + per_block - 1) / per_block;
         if (group == 16)
             hipLaunchKernelGGL(seg_decode_kernel<16>, dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
