@@ -6,10 +6,10 @@
 // computed here one 64-position word at a time and reduced across the wave.
 //
 // A group of threads per packet (part of a wave, a wave or a workgroup): the
-// 64-position words of all segments are dealt to the threads and read from
-// HBM once, as unaligned two-word windows.  Each word is folded into the
+// 128-position windows of all segments are dealt to the threads and read from
+// HBM once, as unaligned three-word spans.  Each window is folded into the
 // thread's partial syndrome of its segment and its message bits (one run of
-// consecutive message indices per word) are ORed into the packet's message
+// consecutive message indices per window) are ORed into the packet's message
 // buffer in LDS; the segment owners then finish the syndromes, flip the one
 // message bit a correctable error hits, and the buffer is stored.  Segment
 // offsets are closed-form (message sizes take two values), so no lookup
@@ -38,9 +38,11 @@ __host__ __device__ inline uint32_t enc_slice_words(uint32_t max_msg_bytes)
     return (8u * max_msg_bytes + 16u * HAMMING_SEG_MAX_T + 63u) / 64u + 3u;
 }
 
+// Message words of the longest packet plus three (a message run ORed in at a
+// bit offset touches up to three words).
 __host__ __device__ inline uint32_t msg_slice_words(uint32_t max_msg_bytes)
 {
-    return (max_msg_bytes + 7u) / 8u + 2u;
+    return (max_msg_bytes + 7u) / 8u + 3u;
 }
 
 // Checksum bits of a shortened segment with k >= 1 message bits: the
@@ -186,7 +188,7 @@ __device__ __forceinline__ uint32_t fold_syndrome(uint64_t x, uint32_t h)
     return v;
 }
 
-constexpr uint32_t kBatch = 4;    // position words a thread loads before it uses them
+constexpr uint32_t kBatch = 4;    // windows a thread loads before it uses them
 
 // Adds a thread's partial syndrome of segment i to the segment's accumulators.
 // Threads whose words cancelled (or that had none) skip the LDS atomics, which
@@ -199,72 +201,78 @@ __device__ __forceinline__ void flush_partial(uint64_t* X, uint32_t* H, uint32_t
     }
 }
 
-// One pass over the position words of every segment of a packet (thread gl
-// takes flat words gl, gl + GROUP, ...), read from HBM as two-word windows.
-// Each word is folded into the thread's partial syndrome of its segment
-// (flushed to X/H in LDS when the thread moves on to the next segment) and
-// its message positions are ORed into the message buffer Mb: for w >= 1 the
-// positions 64w+1..64w+63 of a word are all message positions and so is 64w
-// unless w is a power of two, so a word holds one run of consecutive message
-// bits whose first index is closed-form; word 0 holds the 57 head bits.
-// Mb, X and H must be zero and visible on entry; the result is visible to the
-// group on return.
+// One pass over the windows of every segment of a packet: window v of a
+// segment is positions 128v..128v+127 (bit q of the pair (x0, x1) is position
+// 128v + q), and thread gl takes flat windows gl, gl + GROUP, ...  A window is
+// read from HBM as three words and shifted into place.  It is folded into the
+// thread's partial syndrome of its segment (bits 0..5 of a position are those
+// of q mod 64, bit 6 says which half, the rest are v), flushed to X/H in LDS
+// when the thread moves on to the next segment.  Its message positions are
+// ORed into the message buffer Mb: for v >= 1 only position 128v can be a
+// checksum position (when v is a power of two), so a window holds one run of
+// consecutive message bits whose first index is closed-form; window 0 holds
+// the 57 head bits, the checksum position 64 and 63 more message bits.
+// Mb (mw + 3 words), X and H must be zero and visible on entry; the result is
+// visible to the group on return.
 template <uint32_t GROUP>
 __device__ __forceinline__ void scan_packet(const uint64_t* src, uint32_t ew, const Layout& Lo, uint64_t* Mb,
                                             uint64_t* X, uint32_t* H, uint32_t gl)
 {
-    const uint32_t words = Lo.syndrome_words();
-    // walk state of the next word to load: segment, word, words in the
+    const uint32_t vA = Lo.nA / 128u + 1u, vB = Lo.nB / 128u + 1u;
+    const uint32_t wins = Lo.rem * vA + (Lo.t - Lo.rem) * vB;
+    // walk state of the next window to load: segment, window, windows in the
     // segment, first stream bit, positions, first message bit
-    uint32_t wi = 0, ww = gl, wnw = Lo.rem > 0 ? Lo.nwA : Lo.nwB, wo = 0, wn = Lo.n(0), wK = 0;
+    uint32_t wi = 0, vv = gl, wnv = Lo.rem > 0 ? vA : vB, wo = 0, wn = Lo.n(0), wK = 0;
     uint32_t ci = 0;              // segment of the partial syndrome in xacc/hacc
     uint64_t xacc = 0;
     uint32_t hacc = 0;
-    for (uint32_t g0 = gl; g0 < words; g0 += kBatch * GROUP) {
-        uint64_t lo[kBatch], hi[kBatch];
-        uint32_t qa[kBatch], qb[kBatch], seg[kBatch], wd[kBatch], sh[kBatch], nn[kBatch], kk[kBatch];
+    const uint32_t last = ew - 1u;
+    for (uint32_t g0 = gl; g0 < wins; g0 += kBatch * GROUP) {
+        uint64_t a[kBatch], b[kBatch], c[kBatch];
+        int32_t qw[kBatch];
+        uint32_t seg[kBatch], wd[kBatch], sh[kBatch], nn[kBatch], kk[kBatch];
 #pragma unroll
         for (uint32_t u = 0; u < kBatch; ++u) {
-            // (a slot past the packet's last word stays in the last segment;
-            // it is never used)
-            while (ww >= wnw && wi + 1 < Lo.t) {
-                ww -= wnw;
+            // (a slot past the packet's last window stays in the last
+            // segment; it is never used)
+            while (vv >= wnv && wi + 1 < Lo.t) {
+                vv -= wnv;
                 ++wi;
-                wnw = wi < Lo.rem ? Lo.nwA : Lo.nwB;
+                wnv = wi < Lo.rem ? vA : vB;
                 wo = Lo.o(wi);
                 wn = Lo.n(wi);
                 wK = Lo.K(wi);
             }
-            // position 64ww of segment wi is stream bit s0 (-1, before the
-            // packet, for the first word of segment 0).  The loads are
-            // unconditional, clamped into the packet: for s0 = -1 the stray
-            // bit lands on position 0, and a word past the packet supplies
-            // only positions past the last segment; both are masked below
-            // (slots past the end are never used).
-            const int32_t s0 = int32_t(wo + 64u * ww) - 1;
-            const int32_t q = s0 >> 6;
-            qa[u] = min(uint32_t(max(q, 0)), ew - 1u);
-            qb[u] = min(uint32_t(q + 1), ew - 1u);
+            // position 128vv of segment wi is stream bit s0 (-1, before the
+            // packet, for the first window of segment 0)
+            const int32_t s0 = int32_t(wo + 128u * vv) - 1;
+            qw[u] = s0 >> 6;
             seg[u] = wi;
-            wd[u] = ww;
+            wd[u] = vv;
             sh[u] = uint32_t(s0) & 63u;
             nn[u] = wn;
             kk[u] = wK;
-            ww += GROUP;
+            vv += GROUP;
+        }
+        // Unconditional loads clamped into the packet: for s0 = -1 the stray
+        // bit lands on position 0, and a word past the packet supplies only
+        // positions past the last segment; both are masked below.
+#pragma unroll
+        for (uint32_t u = 0; u < kBatch; ++u) {
+            a[u] = src[min(uint32_t(max(qw[u], 0)), last)];
+            b[u] = src[min(uint32_t(qw[u] + 1), last)];
+            c[u] = src[min(uint32_t(qw[u] + 2), last)];
         }
 #pragma unroll
         for (uint32_t u = 0; u < kBatch; ++u) {
-            lo[u] = src[qa[u]];
-            hi[u] = src[qb[u]];
-        }
-#pragma unroll
-        for (uint32_t u = 0; u < kBatch; ++u) {
-            if (g0 + u * GROUP >= words) break;
-            const uint32_t w = wd[u], s = sh[u];
-            uint64_t x = (lo[u] >> s) | ((hi[u] << 1) << (63u - s));
+            if (g0 + u * GROUP >= wins) break;
+            const uint32_t v = wd[u], s = sh[u];
+            uint64_t x0 = (a[u] >> s) | ((b[u] << 1) << (63u - s));
+            uint64_t x1 = (b[u] >> s) | ((c[u] << 1) << (63u - s));
             // positions past the segment's last one, and position 0
-            const uint32_t top = min(nn[u] - 64u * w, 63u);
-            x &= (~uint64_t(0) >> (63u - top)) & ~uint64_t(w == 0 ? 1u : 0u);
+            const uint32_t top = nn[u] - 128u * v;
+            x0 &= (~uint64_t(0) >> (63u - min(top, 63u))) & ~uint64_t(v == 0 ? 1u : 0u);
+            x1 &= top < 64u ? uint64_t(0) : (~uint64_t(0) >> (63u - min(top - 64u, 63u)));
 
             if (seg[u] != ci) {
                 flush_partial(X, H, ci, xacc, hacc);
@@ -272,19 +280,25 @@ __device__ __forceinline__ void scan_packet(const uint64_t* src, uint32_t ew, co
                 xacc = 0;
                 hacc = 0;
             }
-            xacc ^= x;
-            hacc ^= (__popcll(x) & 1u) ? 64u * w : 0u;
+            const uint64_t f = x0 ^ x1;
+            xacc ^= f;
+            hacc ^= ((uint32_t(__popcll(x1)) & 1u) << 6) ^ ((__popcll(f) & 1u) ? 128u * v : 0u);
 
-            // message bits of the word and the index of the first one (pw:
-            // position 64w is a checksum position, as for w = 0 none is)
-            const uint32_t lw = 31u - __clz(w | 1u);
-            const uint32_t pw = (w & (w - 1u)) == 0u ? 1u : 0u;
-            uint64_t c = x >> pw;
-            if (w == 0) c = head_message(c);
-            const uint32_t b = kk[u] + (w == 0 ? 0u : 64u * w + pw - lw - 8u);
-            const uint32_t bq = b >> 6, bs = b & 63u;
-            atomicOr(reinterpret_cast<unsigned long long*>(&Mb[bq]), c << bs);
-            atomicOr(reinterpret_cast<unsigned long long*>(&Mb[bq + 1]), (c >> 1) >> (63u - bs));
+            // message bits of the window and the index of the first one (pw:
+            // position 128v is a checksum position, as for v = 0 none is)
+            const uint32_t lv = 31u - __clz(v | 1u);
+            const uint32_t pw = (v & (v - 1u)) == 0u ? 1u : 0u;
+            uint64_t c0 = (x0 >> pw) | ((x1 << 1) << (63u - pw));
+            uint64_t c1 = x1 >> pw;
+            if (v == 0) {
+                c0 = head_message(c0) | (c1 << 57);
+                c1 >>= 7;
+            }
+            const uint32_t bb = kk[u] + (v == 0 ? 0u : 128u * v + pw - lv - 9u);
+            const uint32_t bq = bb >> 6, bs = bb & 63u;
+            atomicOr(reinterpret_cast<unsigned long long*>(&Mb[bq]), c0 << bs);
+            atomicOr(reinterpret_cast<unsigned long long*>(&Mb[bq + 1]), ((c0 >> 1) >> (63u - bs)) | (c1 << bs));
+            atomicOr(reinterpret_cast<unsigned long long*>(&Mb[bq + 2]), (c1 >> 1) >> (63u - bs));
         }
     }
     flush_partial(X, H, ci, xacc, hacc);
@@ -310,7 +324,7 @@ struct SegArgs {
 constexpr uint32_t kAccWords = HAMMING_SEG_MAX_T + HAMMING_SEG_MAX_T / 2;
 
 // Decode packet pk with GROUP threads (gl = 0..GROUP-1); Mb is the packet's
-// message buffer in LDS (at least mw + 1 words) and acc its accumulators.
+// message buffer in LDS (at least mw + 3 words) and acc its accumulators.
 // With GROUP < 64 several packets share a wave, so pk, the descriptor and the
 // layout are per-lane values and wave-wide ballots are masked to the group.
 // Every thread of a group takes the same branches at the barriers.
@@ -331,7 +345,7 @@ __device__ __forceinline__ void decode_packet(const SegArgs& a, uint64_t pk, uin
     }
     uint64_t* X = acc;
     uint32_t* H = reinterpret_cast<uint32_t*>(acc + HAMMING_SEG_MAX_T);
-    for (uint32_t w = gl; w <= mw; w += GROUP) Mb[w] = 0;
+    for (uint32_t w = gl; w < mw + 3; w += GROUP) Mb[w] = 0;
     for (uint32_t i = gl; i < t; i += GROUP) {
         X[i] = 0;
         H[i] = 0;
