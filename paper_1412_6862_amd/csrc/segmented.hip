@@ -188,7 +188,6 @@ __device__ __forceinline__ uint32_t fold_syndrome(uint64_t x, uint32_t h)
     return v;
 }
 
-constexpr uint32_t kBatch = 4;    // windows a thread loads before it uses them
 
 // Adds a thread's partial syndrome of segment i to the segment's accumulators.
 // Threads whose words cancelled (or that had none) skip the LDS atomics, which
@@ -204,7 +203,8 @@ __device__ __forceinline__ void flush_partial(uint64_t* X, uint32_t* H, uint32_t
 // One pass over the windows of every segment of a packet: window v of a
 // segment is positions 128v..128v+127 (bit q of the pair (x0, x1) is position
 // 128v + q), and thread gl takes flat windows gl, gl + GROUP, ...  A window is
-// read from HBM as three words and shifted into place.  It is folded into the
+// read from HBM as three words and shifted into place; a thread issues the
+// loads of BATCH windows before it uses the first.  It is folded into the
 // thread's partial syndrome of its segment (bits 0..5 of a position are those
 // of q mod 64, bit 6 says which half, the rest are v), flushed to X/H in LDS
 // when the thread moves on to the next segment.  Its message positions are
@@ -214,7 +214,7 @@ __device__ __forceinline__ void flush_partial(uint64_t* X, uint32_t* H, uint32_t
 // the 57 head bits, the checksum position 64 and 63 more message bits.
 // Mb (mw + 3 words), X and H must be zero and visible on entry; the result is
 // visible to the group on return.
-template <uint32_t GROUP>
+template <uint32_t GROUP, uint32_t BATCH>
 __device__ __forceinline__ void scan_packet(const uint64_t* src, uint32_t ew, const Layout& Lo, uint64_t* Mb,
                                             uint64_t* X, uint32_t* H, uint32_t gl)
 {
@@ -227,12 +227,12 @@ __device__ __forceinline__ void scan_packet(const uint64_t* src, uint32_t ew, co
     uint64_t xacc = 0;
     uint32_t hacc = 0;
     const uint32_t last = ew - 1u;
-    for (uint32_t g0 = gl; g0 < wins; g0 += kBatch * GROUP) {
-        uint64_t a[kBatch], b[kBatch], c[kBatch];
-        int32_t qw[kBatch];
-        uint32_t seg[kBatch], wd[kBatch], sh[kBatch], nn[kBatch], kk[kBatch];
+    for (uint32_t g0 = gl; g0 < wins; g0 += BATCH * GROUP) {
+        uint64_t a[BATCH], b[BATCH], c[BATCH];
+        int32_t qw[BATCH];
+        uint32_t seg[BATCH], wd[BATCH], sh[BATCH], nn[BATCH], kk[BATCH];
 #pragma unroll
-        for (uint32_t u = 0; u < kBatch; ++u) {
+        for (uint32_t u = 0; u < BATCH; ++u) {
             // (a slot past the packet's last window stays in the last
             // segment; it is never used)
             while (vv >= wnv && wi + 1 < Lo.t) {
@@ -258,13 +258,13 @@ __device__ __forceinline__ void scan_packet(const uint64_t* src, uint32_t ew, co
         // bit lands on position 0, and a word past the packet supplies only
         // positions past the last segment; both are masked below.
 #pragma unroll
-        for (uint32_t u = 0; u < kBatch; ++u) {
+        for (uint32_t u = 0; u < BATCH; ++u) {
             a[u] = src[min(uint32_t(max(qw[u], 0)), last)];
             b[u] = src[min(uint32_t(qw[u] + 1), last)];
             c[u] = src[min(uint32_t(qw[u] + 2), last)];
         }
 #pragma unroll
-        for (uint32_t u = 0; u < kBatch; ++u) {
+        for (uint32_t u = 0; u < BATCH; ++u) {
             if (g0 + u * GROUP >= wins) break;
             const uint32_t v = wd[u], s = sh[u];
             uint64_t x0 = (a[u] >> s) | ((b[u] << 1) << (63u - s));
@@ -328,7 +328,7 @@ constexpr uint32_t kAccWords = HAMMING_SEG_MAX_T + HAMMING_SEG_MAX_T / 2;
 // With GROUP < 64 several packets share a wave, so pk, the descriptor and the
 // layout are per-lane values and wave-wide ballots are masked to the group.
 // Every thread of a group takes the same branches at the barriers.
-template <uint32_t GROUP>
+template <uint32_t GROUP, uint32_t BATCH>
 __device__ __forceinline__ void decode_packet(const SegArgs& a, uint64_t pk, uint32_t gl, uint64_t* Mb, uint64_t* acc)
 {
     const hamming_seg_packet d = a.descs[pk];
@@ -352,7 +352,7 @@ __device__ __forceinline__ void decode_packet(const SegArgs& a, uint64_t pk, uin
     }
     group_sync<GROUP>();
 
-    scan_packet<GROUP>(a.enc + d.enc_word_off, uint32_t(ew), Lo, Mb, X, H, gl);
+    scan_packet<GROUP, BATCH>(a.enc + d.enc_word_off, uint32_t(ew), Lo, Mb, X, H, gl);
 
     // checksum owners: thread gl takes segments gl, gl + GROUP, ...; an error
     // at a message position flips that message bit, one at a checksum
@@ -387,7 +387,7 @@ __device__ __forceinline__ void decode_packet(const SegArgs& a, uint64_t pk, uin
 
 // Throughput form: 256 / GROUP packets per block, GROUP threads each (a
 // wave, or a part of one for short packets).
-template <uint32_t GROUP>
+template <uint32_t GROUP, uint32_t BATCH>
 __global__ __launch_bounds__(64 * kSegWaves) void seg_decode_kernel(SegArgs a)
 {
     extern __shared__ uint64_t lds[];
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_decode_kernel(SegArgs a)
     const uint64_t pk = uint64_t(blockIdx.x) * (64 * kSegWaves / GROUP) + slot;
     if (pk >= a.n_packets) return;
     uint64_t* slice = lds + slot * (a.slice_words + kAccWords);
-    decode_packet<GROUP>(a, pk, threadIdx.x % GROUP, slice, slice + a.slice_words);
+    decode_packet<GROUP, BATCH>(a, pk, threadIdx.x % GROUP, slice, slice + a.slice_words);
 }
 
 // Latency form: one packet per block, all four waves on it.
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_decode_wide_kernel(SegArgs
     extern __shared__ uint64_t lds[];
     const uint64_t pk = blockIdx.x;
     if (pk >= a.n_packets) return;
-    decode_packet<64 * kSegWaves>(a, pk, threadIdx.x, lds, lds + a.slice_words);
+    decode_packet<64 * kSegWaves, 2>(a, pk, threadIdx.x, lds, lds + a.slice_words);
 }
 
 __global__ __launch_bounds__(64 * kSegWaves) void seg_encode_kernel(SegArgs a)
@@ -562,12 +562,20 @@ int hamming_decode_segmented(const uint64_t* enc_arena, uint64_t enc_words, cons
         const uint32_t per_block = 64 * kSegWaves / group;
         const size_t lds = size_t(per_block) * (a.slice_words + kAccWords) * 8;
         const uint32_t blocks = (n_packets + per_block - 1) / per_block;
-        if (group == 16)
-            hipLaunchKernelGGL(seg_decode_kernel<16>, dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
+        // windows a thread loads ahead: 2 while a thread has at most about
+        // five windows (the unused slots of a last batch cost loads and walk
+        // steps), 4 above (more loads in flight); measured on the Table 1 grid
+        const bool deep = (8u * max_msg_bytes) / (128u * group) > 5u;
+        if (group == 16 && deep)
+            hipLaunchKernelGGL((seg_decode_kernel<16, 4>), dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
+        else if (group == 16)
+            hipLaunchKernelGGL((seg_decode_kernel<16, 2>), dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
+        else if (group == 32 && deep)
+            hipLaunchKernelGGL((seg_decode_kernel<32, 4>), dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
         else if (group == 32)
-            hipLaunchKernelGGL(seg_decode_kernel<32>, dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
-        else
-            hipLaunchKernelGGL(seg_decode_kernel<64>, dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
+            hipLaunchKernelGGL((seg_decode_kernel<32, 2>), dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
+        else   // 64 threads: at most four windows each (HAMMING_SEG_MAX_BYTES)
+            hipLaunchKernelGGL((seg_decode_kernel<64, 2>), dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
     }
     return hipGetLastError() == hipSuccess ? HAMMING_OK : HAMMING_EDEVICE;
 }
