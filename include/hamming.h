@@ -317,7 +317,7 @@ int hamming_decode_segmented(const uint64_t *enc_arena, uint64_t enc_words, cons
                              uint16_t *syndromes, uint64_t syndrome_count, uint8_t *status, hipStream_t stream);
 
 /* Work assignment of hamming_decode_segmented (no effect on results): the
- * threads that cooperate on one packet, 16 or 32 (part of a wave), 64 (a
+ * threads that cooperate on one packet, 8, 16 or 32 (part of a wave), 64 (a
  * wave) or 256 (a workgroup).  0 lets the library choose: a workgroup per
  * packet for batches of at most 2048 packets (latency), else a group sized to
  * max_msg_bytes (throughput).  Process-wide.  Returns HAMMING_OK or

@@ -386,7 +386,7 @@ __device__ __forceinline__ void decode_packet(const SegArgs& a, uint64_t pk, uin
 }
 
 // Throughput form: 256 / GROUP packets per block, GROUP threads each (a
-// wave, or a part of one for short packets).
+// wave, or a part of one: 8, 16 or 32 threads).
 template <uint32_t GROUP, uint32_t BATCH>
 __global__ __launch_bounds__(64 * kSegWaves) void seg_decode_kernel(SegArgs a)
 {
@@ -490,8 +490,11 @@ std::atomic<uint32_t> g_seg_threads{0};
 uint32_t auto_threads_per_packet(uint32_t n_packets, uint32_t max_msg_bytes)
 {
     if (n_packets <= kWideMaxPackets) return 256;
-    // measured on the Table 1 grid (400..2000-byte packets): 16 threads per
-    // packet beat 32 and 64 at every size
+    // measured on the Table 1 grid (400..2000-byte packets): 8 threads per
+    // packet are fastest at 400 bytes (the per-packet overhead is shared by
+    // eight packets of a wave), tie with 16 at 800, and 16 beat 8, 32 and 64
+    // from 1200 bytes on
+    if (max_msg_bytes <= 640) return 8u;
     return max_msg_bytes <= 2048 ? 16u : (max_msg_bytes <= 3072 ? 32u : 64u);
 }
 
@@ -530,7 +533,7 @@ int64_t hamming_seg_layout(uint32_t msg_bytes, uint32_t t, uint32_t* k_out, uint
 
 int hamming_seg_config_set(uint32_t threads_per_packet)
 {
-    if (threads_per_packet != 0 && threads_per_packet != 16 && threads_per_packet != 32 &&
+    if (threads_per_packet != 0 && threads_per_packet != 8 && threads_per_packet != 16 && threads_per_packet != 32 &&
         threads_per_packet != 64 && threads_per_packet != 256)
         return HAMMING_EINVAL;
     g_seg_threads.store(threads_per_packet);
@@ -566,7 +569,11 @@ int hamming_decode_segmented(const uint64_t* enc_arena, uint64_t enc_words, cons
         // five windows (the unused slots of a last batch cost loads and walk
         // steps), 4 above (more loads in flight); measured on the Table 1 grid
         const bool deep = (8u * max_msg_bytes) / (128u * group) > 5u;
-        if (group == 16 && deep)
+        if (group == 8 && deep)
+            hipLaunchKernelGGL((seg_decode_kernel<8, 4>), dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
+        else if (group == 8)
+            hipLaunchKernelGGL((seg_decode_kernel<8, 2>), dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
+        else if (group == 16 && deep)
             hipLaunchKernelGGL((seg_decode_kernel<16, 4>), dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
         else if (group == 16)
             hipLaunchKernelGGL((seg_decode_kernel<16, 2>), dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);

@@ -300,10 +300,10 @@ def test_host_mapped_mode_argument_checks():
 def test_segmented_mode_config_roundtrip():
     old = hm.hamming_seg_config_get()
     try:
-        for m in (16, 32, 64, 256, 0):
+        for m in (8, 16, 32, 64, 256, 0):
             hm.hamming_seg_config_set(m)
             assert hm.hamming_seg_config_get() == m
-        for bad in (1, 8, 128, 512):
+        for bad in (1, 4, 128, 512):
             with pytest.raises(hm.HammingError):
                 hm.hamming_seg_config_set(bad)
     finally:

@@ -13,7 +13,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-MODES = [16, 32, 64, 256]   # threads per packet
+MODES = [8, 16, 32, 64, 256]   # threads per packet
 
 
 @pytest.fixture
