@@ -477,11 +477,20 @@ def segmented_algorithmic_bytes(msg_bytes: int, t: int) -> float:
     return bits / 8.0 + 32 + msg_bytes + 2 * t + 1
 
 
+def segmented_encode_bytes(msg_bytes: int, t: int) -> float:
+    """Descriptor read + message read + encoded packet write."""
+    import paper_1412_6862_amd as hm
+
+    _, _, bits = hm.hamming_seg_layout(msg_bytes, t)
+    return 32 + msg_bytes + bits / 8.0
+
+
 def segmented_leg(dev, n_packets: int, reps: int, lat_reps: int):
     """The paper's packets (Sec. II, Table 1 grid): M bytes in t shortened
-    segments.  Per shape: a batch of n_packets packets (encoded on the GPU,
-    flips from the seeded channel) decoded in one launch, and the latency of
-    a one-packet launch."""
+    segments.  Per shape: a batch of n_packets packets encoded on the GPU in
+    one launch (the transmitter half, timed too), flips from the seeded
+    channel, the batch decoded in one launch, and the latency of a one-packet
+    decode launch."""
     import numpy as np
     import torch
 
@@ -494,7 +503,8 @@ def segmented_leg(dev, n_packets: int, reps: int, lat_reps: int):
         b = hm.SegmentedBatch(n_packets, mb, t, device=dev)
         seed = synth.workload_seed("bench-seg", mb, t)
         b.msg.copy_(synth.draws_torch(seed, 0, n_packets * b.msg_stride, dev))
-        b.encode()
+        t_enc = time_events(lambda: b.encode(stream), stream, 3, reps)
+        enc_med = t_enc[len(t_enc) // 2]
         k, r, _ = hm.hamming_seg_layout(mb, t)
         n = np.asarray(k) + np.asarray(r)
         starts = np.concatenate([[0], np.cumsum(n)[:-1]])
@@ -515,6 +525,8 @@ def segmented_leg(dev, n_packets: int, reps: int, lat_reps: int):
                      "packets_per_s": round(n_packets / med * 1e3, 0),
                      "us_per_packet_batched": round(med * 1e3 / n_packets, 5),
                      "GBps": round(algo / med / 1e6, 1), "frac_hbm": round(algo / med / 1e6 / HBM_PEAK_GBPS, 4),
+                     "encode_us": round(enc_med * 1e3, 1),
+                     "encode_frac_hbm": round(segmented_encode_bytes(mb, t) * n_packets / enc_med / 1e6 / HBM_PEAK_GBPS, 4),
                      "single_packet_p50_us": round(float(np.percentile(lat, 50)), 2),
                      "single_packet_p99_us": round(float(np.percentile(lat, 99)), 2),
                      "status_clean_corrected_uncorrectable": st})

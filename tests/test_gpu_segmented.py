@@ -85,8 +85,9 @@ def test_segmented_parity_error_extremes(gpu_device, seg_mode, p_single, p_doubl
         assert (st == 1).all()
 
 
+@pytest.mark.parametrize("seg_mode", MODES + [0], indirect=True)
 @pytest.mark.parametrize("msg_bytes,t", [(400, 2), (2000, 6), (1, 1), (13, 5), (4096, 1), (4096, 32), (255, 7)])
-def test_segmented_encoder_parity(gpu_device, msg_bytes, t):
+def test_segmented_encoder_parity(gpu_device, seg_mode, msg_bytes, t):
     import torch
 
     P = 157
@@ -180,12 +181,16 @@ def test_segmented_max_msg_bytes_bound_rejects_longer_packets(gpu_device, seg_mo
     assert (b.status.cpu().numpy() == hm.HAMMING_SEG_INVALID).all()
 
 
-def test_segmented_full_size_sampled(gpu_device):
-    """2^20 packets of 1500 bytes in 4 segments, encoded on the GPU; a sample
-    of packets is checked against the oracle one by one."""
+@pytest.mark.parametrize("P,mb,t", [(1 << 20, 1500, 4), (1 << 19, 400, 6), (1 << 19, 1200, 4), (1 << 19, 2000, 6)])
+def test_segmented_full_size_sampled(gpu_device, P, mb, t):
+    """Full-size batches in the library's own launch choice (the Table 1 grid
+    is decoded with 2^19 packets per shape: 400 bytes take 8 threads per
+    packet, 1200 and 2000 bytes 16, with two and four windows loaded ahead),
+    encoded on the GPU; a sample of packets is checked against the oracle one
+    by one."""
     import torch
 
-    P, mb, t = 1 << 20, 1500, 4
+    assert hm.hamming_seg_config_get() == 0
     b = hm.SegmentedBatch(P, mb, t, device=gpu_device)
     seed = synth.workload_seed("gpu-seg-full", mb, t)
     w = synth.draws_torch(seed, 0, P * b.msg_stride, gpu_device)
