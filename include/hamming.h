@@ -409,10 +409,11 @@ int hamming_tune_load(const char *cache_path);
 
 /*
  * A server decodes requests (one packet each) taken from a device-resident
- * codeword pool, batching whatever is waiting into one hamming_decode_batch
- * launch as soon as one of its in-flight batch slots is free, so requests that
- * arrive while earlier batches run are admitted and overlap with them on the
- * device.  A request is admitted when its outputs fit in the server's output
+ * codeword pool, batching whatever is waiting as soon as one of its in-flight
+ * batch slots is free, so requests that arrive while earlier batches run are
+ * admitted and overlap with them on the device.  A batch of at most 16
+ * requests and 2^20 codewords is one decode launch with its descriptors in
+ * the kernel arguments; a larger one is one hamming_decode_batch call.  A request is admitted when its outputs fit in the server's output
  * pool (the device-memory admission cap); until then it waits in FIFO order.
  * The server is driven by the caller (hamming_server_progress) and keeps no
  * thread of its own; one server must not be used from two threads at once.

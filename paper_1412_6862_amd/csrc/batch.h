@@ -68,4 +68,26 @@ constexpr uint64_t kWavesPerBlockHost = 4;
 
 hipError_t launch_batch(const BatchArgs& a, int schedule, uint32_t grid, hipStream_t stream);
 
+// A batch small enough to travel in the kernel arguments: its descriptors
+// and the exclusive prefix sum of their tile counts, computed on the host by
+// a caller that has validated the descriptors itself (the server).  One
+// launch then replaces the descriptor copy, the plan and the two map kernels.
+constexpr uint32_t kSmallBatchMax = 16;
+struct SmallBatch {
+    const uint64_t* cw_arena;
+    uint64_t* data_arena;
+    uint8_t* errpos_arena;
+    uint32_t n;
+    uint32_t reserved;
+    uint64_t tile_start[kSmallBatchMax + 1];
+    hamming_packet descs[kSmallBatchMax];
+};
+
+// Codewords per lane of a tile of r-bit codewords in a batch schedule (a
+// tile is 64 lanes); 0 for an unknown schedule or r.
+uint32_t schedule_lane_width(int schedule, uint32_t r);
+
+// Decodes a small batch whose tile_start[n] tiles are at least one.
+hipError_t launch_small_batch(const SmallBatch& b, int schedule, hipStream_t stream);
+
 }  // namespace hm

@@ -15,6 +15,9 @@
 //    (plus a 64-lane probe when a fine entry spans several tiles), then
 //    decodes the tile exactly as the plain kernel would.  A grid smaller than
 //    the batch loops.
+// A batch of at most kSmallBatchMax packets validated by its caller can
+// instead carry its descriptors and tile prefix sums in the kernel arguments
+// of decode_small_batch_kernel: one launch, no copy and no maps.
 // Each packet's output is the same words a plain call would write.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -181,17 +184,30 @@ __device__ __forceinline__ uint32_t probe_packet(const uint64_t* ts, uint32_t n,
 }
 
 template <int R, int U>
-__device__ __forceinline__ void decode_packet_tile(const hamming_packet& d, uint64_t tl, const BatchArgs& a,
-                                                   uint32_t* lds)
+__device__ __forceinline__ void decode_packet_tile(const hamming_packet& d, uint64_t tl, const uint64_t* cw_arena,
+                                                   uint64_t* data_arena, uint8_t* errpos_arena, uint32_t* lds)
 {
-    const uint64_t* cw = a.cw_arena + d.in_word_off;
-    uint64_t* data = a.data_arena + d.data_word_off;
-    uint8_t* ep = (d.errpos_off == HAMMING_NO_ERRPOS) ? nullptr : a.errpos_arena + d.errpos_off;
+    const uint64_t* cw = cw_arena + d.in_word_off;
+    uint64_t* data = data_arena + d.data_word_off;
+    uint8_t* ep = (d.errpos_off == HAMMING_NO_ERRPOS) ? nullptr : errpos_arena + d.errpos_off;
     uint32_t flags = 0;
     if ((reinterpret_cast<uintptr_t>(cw) & 15u) == 0) flags |= kFlagIn16;
     if (ep && (reinterpret_cast<uintptr_t>(ep) % U) == 0) flags |= kFlagEpVec;
     if ((reinterpret_cast<uintptr_t>(data) & 15u) == 0) flags |= kFlagOut16;
     decode_tile<R, U>(cw, d.n_cw, tl, data, message_words(d.n_cw, R), ep, lds, flags);
+}
+
+template <class S>
+__device__ __forceinline__ void decode_any_tile(const hamming_packet& d, uint64_t tl, const uint64_t* cw_arena,
+                                                uint64_t* data_arena, uint8_t* errpos_arena, uint32_t* lds)
+{
+    switch (d.r) {
+    case 3: decode_packet_tile<3, S::u[0]>(d, tl, cw_arena, data_arena, errpos_arena, lds); break;
+    case 4: decode_packet_tile<4, S::u[1]>(d, tl, cw_arena, data_arena, errpos_arena, lds); break;
+    case 5: decode_packet_tile<5, S::u[2]>(d, tl, cw_arena, data_arena, errpos_arena, lds); break;
+    case 6: decode_packet_tile<6, S::u[3]>(d, tl, cw_arena, data_arena, errpos_arena, lds); break;
+    default: decode_packet_tile<7, S::u[4]>(d, tl, cw_arena, data_arena, errpos_arena, lds); break;
+    }
 }
 
 template <class S>
@@ -223,14 +239,26 @@ void decode_batch_kernel(
         if (gf) p = probe_packet(ts, n, t, p);
         const hamming_packet d = descs[p];
         const uint64_t tl = t - ts[p];
-        switch (d.r) {
-        case 3: decode_packet_tile<3, S::u[0]>(d, tl, a, lds); break;
-        case 4: decode_packet_tile<4, S::u[1]>(d, tl, a, lds); break;
-        case 5: decode_packet_tile<5, S::u[2]>(d, tl, a, lds); break;
-        case 6: decode_packet_tile<6, S::u[3]>(d, tl, a, lds); break;
-        default: decode_packet_tile<7, S::u[4]>(d, tl, a, lds); break;
-        }
+        decode_any_tile<S>(d, tl, a.cw_arena, a.data_arena, a.errpos_arena, lds);
     }
+}
+
+// The small-batch form: one tile per wave, the packet found by a scan of the
+// prefix sums in the kernel arguments (at most kSmallBatchMax entries, scalar
+// loads), then the same tile decode.
+template <class S>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(S::waves_per_simd)))
+void decode_small_batch_kernel(SmallBatch b)
+{
+    __shared__ u32x4 lds_raw[kWavesPerBlock][S::LDS_MAX / 4];
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t* lds = reinterpret_cast<uint32_t*>(&lds_raw[wave][0]);
+    const uint64_t t = uint64_t(blockIdx.x) * kWavesPerBlock + wave;
+    if (t >= b.tile_start[b.n]) return;
+    uint32_t p = 0;
+    while (p + 1 < b.n && b.tile_start[p + 1] <= t) ++p;    // packets without tiles are passed over
+    const hamming_packet d = b.descs[p];
+    decode_any_tile<S>(d, t - b.tile_start[p], b.cw_arena, b.data_arena, b.errpos_arena, lds);
 }
 
 template <class S>
@@ -248,6 +276,39 @@ static hipError_t launch_batch_s(const BatchArgs& a, uint32_t grid, hipStream_t 
     hipLaunchKernelGGL((decode_batch_kernel<S>), dim3(grid), dim3(kBlockThreads), 0, stream, a, a.ws, a.fine,
                        a.tile_start, a.descs);
     return hipGetLastError();
+}
+
+template <class S>
+static hipError_t launch_small_s(const SmallBatch& b, hipStream_t stream)
+{
+    const uint64_t blocks = (b.tile_start[b.n] + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks == 0 || blocks > 0xFFFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((decode_small_batch_kernel<S>), dim3(uint32_t(blocks)), dim3(kBlockThreads), 0, stream, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_small_batch(const SmallBatch& b, int schedule, hipStream_t stream)
+{
+    if (b.n < 1 || b.n > kSmallBatchMax) return hipErrorInvalidValue;
+    switch (schedule) {
+    case 0: return launch_small_s<Sched0>(b, stream);
+    case 1: return launch_small_s<Sched1>(b, stream);
+    case 2: return launch_small_s<Sched2>(b, stream);
+    case 3: return launch_small_s<Sched3>(b, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+uint32_t schedule_lane_width(int schedule, uint32_t r)
+{
+    if (r < 3 || r > 7) return 0;
+    switch (schedule) {
+    case 0: return uint32_t(Sched0::u[r - 3]);
+    case 1: return uint32_t(Sched1::u[r - 3]);
+    case 2: return uint32_t(Sched2::u[r - 3]);
+    case 3: return uint32_t(Sched3::u[r - 3]);
+    default: return 0;
+    }
 }
 
 hipError_t launch_batch(const BatchArgs& a, int schedule, uint32_t grid, hipStream_t stream)

@@ -3,8 +3,10 @@
 //
 // Flow of one request: submit -> FIFO queue -> admission (its outputs are
 // carved from the output pool) -> placed in the next batch of a free slot ->
-// the slot copies its descriptors to the device and replays its batch graph
-// on its own stream -> progress() sees the slot's event complete -> a
+// the slot launches the batch on its own stream: a batch of at most 16
+// requests and 2^20 codewords is one decode launch with its descriptors in
+// the kernel arguments, a larger one copies its descriptors to the device and
+// replays its batch graph -> progress() sees the slot's event complete -> a
 // completion record is queued (and the outputs freed when auto_release).
 // New batches launch whenever a slot is free, so arrivals overlap with
 // batches already on the GPU.
@@ -23,11 +25,21 @@
 #include <new>
 #include <vector>
 
+#include "batch.h"
 #include "hamming.h"
 
 namespace {
 
 constexpr uint64_t kAlign = 256;   // output allocations start on 256-byte boundaries
+
+// Batches of at most hm::kSmallBatchMax requests and this many codewords are
+// decoded in one launch with their descriptors in the kernel arguments;
+// others go through hamming_decode_batch.  Measured on the serving trace of
+// the bench (256 streams, requests of 256..2^18 codewords): p50 at 10% load
+// 22-31 us against 63-70 us; without the codeword bound the one-launch form
+// also took large batches and its p50 at 70% load rose from 170-187 us to
+// 224-242 us.
+constexpr uint64_t kDirectMaxCodewords = uint64_t(1) << 20;
 
 uint64_t round_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
@@ -193,6 +205,30 @@ int reap(hamming_server* s)
     return HAMMING_OK;
 }
 
+// A batch of at most hm::kSmallBatchMax requests: the descriptors (checked
+// at submission, outputs carved from the pool) and their tile prefix sums go
+// to the decode kernel in its arguments, in one launch.
+int launch_small(hamming_server* s, const hamming_packet* descs, uint32_t n, hipStream_t stream)
+{
+    int schedule = 0, use_graph = 0;
+    uint32_t xcd_chunk = 0, grid_cap = 0;
+    if (hamming_batch_config_get(&schedule, &xcd_chunk, &grid_cap, &use_graph) != HAMMING_OK) return HAMMING_EDEVICE;
+    hm::SmallBatch b{};
+    b.cw_arena = s->pool;
+    b.data_arena = reinterpret_cast<uint64_t*>(s->out_base);
+    b.errpos_arena = s->out_base;
+    b.n = n;
+    b.tile_start[0] = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        b.descs[i] = descs[i];
+        const uint64_t cwt = 64ull * hm::schedule_lane_width(schedule, descs[i].r);
+        if (cwt == 0) return HAMMING_EINVAL;
+        b.tile_start[i + 1] = b.tile_start[i] + (descs[i].n_cw + cwt - 1) / cwt;
+    }
+    if (b.tile_start[n] == 0) return HAMMING_OK;                 // nothing but empty requests
+    return hm::launch_small_batch(b, schedule, stream) == hipSuccess ? HAMMING_OK : HAMMING_EDEVICE;
+}
+
 int launch(hamming_server* s)
 {
     for (auto& sl : s->slots) {
@@ -220,21 +256,26 @@ int launch(hamming_server* s)
             ++n;
         }
         if (n == 0) break;                                      // the head of the queue does not fit
-        *reinterpret_cast<uint32_t*>(sl.host) = n;
-        if (hipMemcpyAsync(sl.n_dev, sl.host, 8 + uint64_t(n) * sizeof(hamming_packet), hipMemcpyHostToDevice,
-                           sl.stream) != hipSuccess)
-            return HAMMING_EDEVICE;
-        uint64_t hint = s->cfg.max_batch_codewords;
-        for (uint64_t tier : kTiers)
-            if (cws <= tier && tier < hint) {
-                hint = tier;
-                break;
-            }
-        const int rc = hamming_decode_batch(s->pool, s->pool_words, sl.descs_dev, sl.n_dev,
-                                            s->cfg.max_batch_packets, hint, reinterpret_cast<uint64_t*>(s->out_base),
-                                            s->alloc.size() / 8, s->out_base, s->alloc.size(), nullptr, sl.ws,
-                                            sl.ws_bytes, sl.stream);
-        if (rc != HAMMING_OK) return rc;
+        if (n <= hm::kSmallBatchMax && cws <= kDirectMaxCodewords) {
+            const int rc = launch_small(s, descs, n, sl.stream);
+            if (rc != HAMMING_OK) return rc;
+        } else {
+            *reinterpret_cast<uint32_t*>(sl.host) = n;
+            if (hipMemcpyAsync(sl.n_dev, sl.host, 8 + uint64_t(n) * sizeof(hamming_packet), hipMemcpyHostToDevice,
+                               sl.stream) != hipSuccess)
+                return HAMMING_EDEVICE;
+            uint64_t hint = s->cfg.max_batch_codewords;
+            for (uint64_t tier : kTiers)
+                if (cws <= tier && tier < hint) {
+                    hint = tier;
+                    break;
+                }
+            const int rc = hamming_decode_batch(s->pool, s->pool_words, sl.descs_dev, sl.n_dev,
+                                                s->cfg.max_batch_packets, hint,
+                                                reinterpret_cast<uint64_t*>(s->out_base), s->alloc.size() / 8,
+                                                s->out_base, s->alloc.size(), nullptr, sl.ws, sl.ws_bytes, sl.stream);
+            if (rc != HAMMING_OK) return rc;
+        }
         if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return HAMMING_EDEVICE;
         sl.first = first;
         sl.count = n;

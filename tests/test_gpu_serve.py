@@ -83,6 +83,30 @@ def test_serve_results_same_alone_in_mix_and_oracle(gpu_device):
         srv.close()
 
 
+def test_serve_large_batch_through_the_batch_graph(gpu_device):
+    """Batches above 16 requests go through hamming_decode_batch (descriptor
+    copy, plan, maps, decode) rather than the one-launch small-batch form the
+    other tests exercise; the results must be the same."""
+    rng = np.random.default_rng(11)
+    n = 40
+    sizes = [int(rng.choice([0, 1, 63, 64, 65, 300, 4097])) for _ in range(n)]
+    rs = [int(rng.integers(3, 8)) for _ in range(n)]
+    pool, offs, ys = _pool(4, sizes, rs)
+    cw = _to_dev(pool, gpu_device)
+    srv = hm.Server(cw, slots=2, max_batch_packets=64, max_batch_codewords=1 << 30, output_pool_bytes=64 << 20)
+    try:
+        ids = {srv.submit(offs[i], sizes[i], rs[i]): i for i in range(n)}
+        got = _drain(srv, n)
+        assert srv.stats()["batches"] == 1
+        for rid, c in got.items():
+            i = ids[rid]
+            if sizes[i]:
+                _check_request(srv, c, ys[i], rs[i], cw, offs[i])
+            srv.release(rid)
+    finally:
+        srv.close()
+
+
 def test_serve_batches_overlap_in_flight(gpu_device):
     sizes = [1 << 20] * 6
     rs = [5, 6, 7, 4, 5, 6]
