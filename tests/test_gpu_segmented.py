@@ -170,6 +170,57 @@ def test_segmented_mixed_shapes_offsets_and_invalid_descriptors(gpu_device, seg_
 
 
 @pytest.mark.parametrize("seg_mode", MODES, indirect=True)
+def test_segmented_encoder_mixed_shapes_offsets_and_invalid_descriptors(gpu_device, seg_mode):
+    """The encoder on packets of mixed shapes at scattered offsets: each valid
+    packet's encoded words equal the oracle's (tail bits 0), and the words
+    between packets and those of rejected descriptors are left as they were."""
+    import torch
+
+    rng = np.random.default_rng(8)
+    P = 300
+    shapes = [(int(rng.integers(1, 2100)), int(rng.integers(1, 9))) for _ in range(P)]
+    shapes = [(mb, min(t, 8 * mb)) for mb, t in shapes]
+    d = np.zeros(P, dtype=hm.seg_packet_dtype())
+    enc_off = msg_off = 0
+    msgs = []
+    for q, (mb, t) in enumerate(shapes):
+        ew = (oracle.seg_layout(mb, t)[3] + 63) // 64
+        d[q] = (enc_off, msg_off, mb, t, 0)
+        msgs.append(synth.packet_bytes(synth.workload_seed("gpu-seg-enc-mix", q), 1, mb)[0])
+        enc_off += ew + int(rng.integers(0, 3))
+        msg_off += (mb + 7) // 8 + int(rng.integers(0, 2))
+    bad = {3: dict(t=0), 11: dict(t=33), 19: dict(msg_bytes=0), 27: dict(msg_bytes=2101),
+           35: dict(enc_word_off=enc_off + 10), 43: dict(msg_word_off=msg_off), 51: dict(t=9, msg_bytes=1)}
+    for q, kv in bad.items():
+        for f, v in kv.items():
+            d[q][f] = v
+    marena = np.frombuffer(rng.integers(0, 256, msg_off * 8, dtype=np.uint8).tobytes(), dtype=np.uint8).copy()
+    for q, (mb, t) in enumerate(shapes):
+        if q not in bad:
+            mo = int(d[q]["msg_word_off"]) * 8
+            marena[mo:mo + mb] = msgs[q]                    # bytes past M stay random: they are ignored
+    dev = gpu_device
+    msg_t = torch.from_numpy(marena.view(np.int64).copy()).to(dev)
+    enc_t = torch.full((enc_off,), 0x5A5A5A5A5A5A5A5A, dtype=torch.int64, device=dev)
+    desc_t = torch.from_numpy(d.view(np.uint8)).to(dev)
+    hm.hamming_encode_segmented(msg_t, msg_t.numel(), desc_t, P, 2100, enc_t, enc_t.numel())
+    torch.cuda.synchronize()
+    enc = enc_t.cpu().numpy().view(np.uint8)
+    written = np.zeros(enc.size, dtype=bool)
+    for q, (mb, t) in enumerate(shapes):
+        if q in bad:
+            continue
+        eo = int(d[q]["enc_word_off"]) * 8
+        nbytes = (oracle.seg_layout(mb, t)[3] + 63) // 64 * 8
+        want = np.zeros(nbytes, dtype=np.uint8)
+        ref = oracle.seg_encode(msgs[q], t)
+        want[:ref.size] = ref
+        assert np.array_equal(enc[eo:eo + nbytes], want), q
+        written[eo:eo + nbytes] = True
+    assert (enc[~written] == 0x5A).all()
+
+
+@pytest.mark.parametrize("seg_mode", MODES, indirect=True)
 def test_segmented_max_msg_bytes_bound_rejects_longer_packets(gpu_device, seg_mode):
     import torch
 
