@@ -295,7 +295,8 @@ typedef struct hamming_seg_packet {
 int64_t hamming_seg_layout(uint32_t msg_bytes, uint32_t t, uint32_t *k_out, uint32_t *r_out);
 
 /*
- * Decode n_packets segmented packets, one wave per packet.
+ * Decode n_packets segmented packets, a group of threads per packet (see
+ * hamming_seg_config_set).
  *   enc_arena, enc_words : device, the encoded packets (8-byte aligned).
  *   descs               : device, n_packets descriptors (8-byte aligned).
  *   max_msg_bytes       : an upper bound of every packet's msg_bytes,
@@ -316,8 +317,8 @@ int hamming_decode_segmented(const uint64_t *enc_arena, uint64_t enc_words, cons
                              uint32_t n_packets, uint32_t max_msg_bytes, uint64_t *msg_arena, uint64_t msg_words,
                              uint16_t *syndromes, uint64_t syndrome_count, uint8_t *status, hipStream_t stream);
 
-/* Work assignment of hamming_decode_segmented (no effect on results): the
- * threads that cooperate on one packet, 8, 16 or 32 (part of a wave), 64 (a
+/* Work assignment of hamming_decode_segmented and hamming_encode_segmented
+ * (no effect on results): the threads that cooperate on one packet, 8, 16 or 32 (part of a wave), 64 (a
  * wave) or 256 (a workgroup).  0 lets the library choose: a workgroup per
  * packet for batches of at most 2048 packets (latency), else a group sized to
  * max_msg_bytes (throughput).  Process-wide.  Returns HAMMING_OK or
