@@ -86,6 +86,36 @@ def test_serve_results_same_alone_in_mix_and_oracle(gpu_device):
         srv.close()
 
 
+@pytest.mark.parametrize("schedule", [0, 1, 2, 3])
+def test_serve_small_batches_under_every_batch_schedule(gpu_device, schedule):
+    """The one-launch small-batch form counts tiles on the host with the lane
+    widths of the batch schedule in force; every schedule must give the same
+    results."""
+    rng = np.random.default_rng(20 + schedule)
+    n = 24
+    sizes = [int(rng.choice([1, 64, 100, 513, 2048, 9000])) for _ in range(n)]
+    rs = [3 + i % 5 for i in range(n)]
+    pool, offs, ys = _pool(10 + schedule, sizes, rs)
+    cw = _to_dev(pool, gpu_device)
+    old = hm.hamming_batch_config_get()
+    hm.hamming_batch_config_set(schedule, old[1], old[2], old[3])
+    srv = hm.Server(cw, slots=2, max_batch_packets=6, max_batch_codewords=1 << 20, output_pool_bytes=64 << 20)
+    try:
+        ids = {}
+        for i in range(n):
+            ids[srv.submit(offs[i], sizes[i], rs[i])] = i
+            if i % 3 == 2:
+                srv.progress()
+        got = _drain(srv, n)
+        for rid, c in got.items():
+            i = ids[rid]
+            _check_request(srv, c, ys[i], rs[i], cw, offs[i])
+            srv.release(rid)
+    finally:
+        srv.close()
+        hm.hamming_batch_config_set(*old)
+
+
 def test_serve_large_batch_through_the_batch_graph(gpu_device):
     """Batches above 16 requests go through hamming_decode_batch (descriptor
     copy, plan, maps, decode) rather than the one-launch small-batch form the
