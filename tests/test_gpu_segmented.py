@@ -220,6 +220,40 @@ def test_segmented_encoder_mixed_shapes_offsets_and_invalid_descriptors(gpu_devi
     assert (enc[~written] == 0x5A).all()
 
 
+# segments that end at each boundary of a 128-position window (n mod 128 = 62, 63, 127, 1, 64, 126):
+# the masks of a window's upper and lower halves switch there
+WINDOW_EDGE_SHAPES = [(56, 8), (57, 8), (120, 8), (121, 8), (184, 8), (123, 4)]
+
+
+@pytest.mark.parametrize("seg_mode", MODES, indirect=True)
+@pytest.mark.parametrize("msg_bytes,t", WINDOW_EDGE_SHAPES)
+def test_segmented_segments_ending_at_window_boundaries(gpu_device, seg_mode, msg_bytes, t):
+    import torch
+
+    P = 700
+    n = oracle.seg_layout(msg_bytes, t)[2]
+    assert len({x % 128 for x in n}) == 1
+    b = hm.SegmentedBatch(P, msg_bytes, t, device=gpu_device)
+    seed = synth.workload_seed("gpu-seg-edge", msg_bytes, t)
+    msgs = synth.packet_bytes(seed, P, msg_bytes)
+    clean = oracle.seg_encode_many(msgs, t, row_bytes=b.enc_stride * 8)
+    enc = _received(seed, P, msg_bytes, t, b.enc_stride * 8, 0.4, 0.2)
+    b.enc.copy_(torch.from_numpy(np.ascontiguousarray(enc).reshape(-1).view(np.int64)).to(gpu_device))
+    b.decode()
+    torch.cuda.synchronize()
+    m_ref, s_ref, st_ref = oracle.seg_decode_many(enc, msg_bytes, t)
+    got = b.msg.cpu().numpy().view(np.uint8).reshape(P, -1)[:, :msg_bytes]
+    assert np.array_equal(got, m_ref)
+    assert np.array_equal(b.syndromes.cpu().numpy().view(np.uint16).reshape(P, t), s_ref)
+    assert np.array_equal(b.status.cpu().numpy(), st_ref)
+    rows = np.zeros((P, b.msg_stride * 8), dtype=np.uint8)
+    rows[:, :msg_bytes] = msgs
+    b.msg.copy_(torch.from_numpy(rows.reshape(-1).view(np.int64)).to(gpu_device))
+    b.encode()
+    torch.cuda.synchronize()
+    assert np.array_equal(b.enc.cpu().numpy().view(np.uint8).reshape(P, -1), clean)
+
+
 @pytest.mark.parametrize("seg_mode", MODES, indirect=True)
 def test_segmented_max_msg_bytes_bound_rejects_longer_packets(gpu_device, seg_mode):
     import torch
