@@ -437,6 +437,34 @@ def sizes_leg(dev):
                         "10% single-bit errors", "rows": rows}
 
 
+def encode_leg(dev, reps: int):
+    """The transmitter half: the plain encode of 2^26 messages per r = 3..6
+    (2^25 for r = 7) from a device-resident dense message stream, as one
+    launch each; algorithmic bytes = message read (k/8 per codeword) +
+    codeword write (8 or 16 bytes)."""
+    import torch
+
+    import paper_1412_6862_amd as hm
+    import synth
+
+    stream = torch.cuda.current_stream()
+    rows = []
+    for r in (3, 4, 5, 6, 7):
+        n = 1 << (25 if r == 7 else 26)
+        k = hm.hamming_message_bits(r)
+        msg = synth.message_stream_torch(synth.workload_seed("bench-encode", r), n, r, dev)
+        out = torch.empty(n * hm.words_per_codeword(r), dtype=torch.int64, device=dev)
+        t = time_events(lambda: hm.hamming_encode(msg, n, r, out, stream), stream, 3, reps)
+        med = t[len(t) // 2]
+        algo = n * (k / 8.0 + 8.0 * hm.words_per_codeword(r))
+        rows.append({"r": r, "n_cw": n, "us_p50": round(med * 1e3, 2),
+                     "GBps": round(algo / med / 1e6, 1), "frac_hbm": round(algo / med / 1e6 / HBM_PEAK_GBPS, 4)})
+        del msg, out
+    torch.cuda.empty_cache()
+    return {"workload": "plain encode, 2^26 codewords per r = 3..6 and 2^25 for r = 7, messages resident in HBM",
+            "rows": rows}
+
+
 def planes_leg(dev, reps: int):
     """Bit-plane input layout against the natural layout on the same received
     words: 2^26 codewords (2^25 for r = 7), 10% single-bit errors."""
@@ -637,9 +665,9 @@ def main() -> int:
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner before timing instead of loading the committed shapes")
     ap.add_argument("--seg-packets", type=int, default=1 << 19)
-    ap.add_argument("--legs", default="latency,sizes,r7,batch,serve,host,seg,planes",
+    ap.add_argument("--legs", default="latency,sizes,r7,batch,serve,host,seg,planes,encode",
                     help="extra legs after the plain one (which gives the reported value): "
-                         "comma-separated subset of latency,sizes,r7,batch,serve,host,seg,planes, or none")
+                         "comma-separated subset of latency,sizes,r7,batch,serve,host,seg,planes,encode, or none")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (counter calibration)")
     args = ap.parse_args()
@@ -782,6 +810,8 @@ def main() -> int:
         out["host_pipeline"] = host_leg(dev, 3)
     if "planes" in legs:
         out["planes"] = planes_leg(dev, 10)
+    if "encode" in legs:
+        out["encode"] = encode_leg(dev, 10)
     if "seg" in legs:
         out["segmented"] = segmented_leg(dev, args.seg_packets, 5, 200)
     if not args.no_cpu:

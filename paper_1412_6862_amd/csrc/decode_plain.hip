@@ -1,6 +1,5 @@
-// Plain packet decode and encode kernels for gfx950.  The per-wave tile
-// decode lives in tile.h; this file holds the plain grid over one packet and
-// the encoder.
+// Plain packet decode kernel for gfx950.  The per-wave tile decode lives in
+// tile.h; this file holds the plain grid over one packet and its launcher.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -24,33 +23,6 @@ __global__ __launch_bounds__(kBlockThreads) void decode_plain_kernel(
     for (uint64_t t = uint64_t(xcd_block(blockIdx.x, gridDim.x, xcd_chunk)) * kWavesPerBlock + wave; t < n_tiles;
          t += waves)
         decode_tile<R, U>(cw, n_cw, t, data, data_words, errpos, lds, flags);
-}
-
-// ---- encoder: one codeword per thread --------------------------------------
-template <int R>
-__global__ __launch_bounds__(256) void encode_plain_kernel(const uint32_t* __restrict__ stream,
-                                                           uint64_t stream_dwords, uint64_t n_cw,
-                                                           uint64_t* __restrict__ cw_out)
-{
-    using C = Code<R>;
-    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n_cw; i += stride) {
-        const uint64_t o = i * C::K;
-        const uint64_t d = o >> 5;
-        const uint32_t sh = uint32_t(o & 31u);
-        uint32_t raw[C::PW + 1];
-#pragma unroll
-        for (int q = 0; q <= C::PW; ++q) raw[q] = (d + q < stream_dwords) ? stream[d + q] : 0u;
-        uint32_t p[C::PW];
-#pragma unroll
-        for (int q = 0; q < C::PW; ++q) p[q] = __builtin_amdgcn_alignbit(raw[q + 1], raw[q], sh);
-        if constexpr (C::K % 32 != 0) p[C::PW - 1] &= (1u << (C::K % 32)) - 1u;
-        uint32_t a[C::DW];
-        deposit<R>(p, a);
-        set_checksum_bits<R>(a, checksum<R>(a));
-#pragma unroll
-        for (int q = 0; q < C::WPC; ++q) cw_out[i * C::WPC + q] = uint64_t(a[2 * q]) | (uint64_t(a[2 * q + 1]) << 32);
-    }
 }
 
 // ---- launchers ----------------------------------------------------------------
@@ -95,31 +67,6 @@ hipError_t launch_decode(const DecodeLaunch& L, hipStream_t stream)
     case 5: return launch_decode_r<5>(L, stream);
     case 6: return launch_decode_r<6>(L, stream);
     case 7: return launch_decode_r<7>(L, stream);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <int R>
-static hipError_t launch_encode_r(const void* stream_in, uint64_t n_cw, uint64_t* out, hipStream_t stream)
-{
-    using C = Code<R>;
-    const uint64_t dwords = 2 * ((n_cw * C::K + 63) / 64);
-    uint64_t blocks = (n_cw + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((encode_plain_kernel<R>), dim3(uint32_t(blocks)), dim3(256), 0, stream,
-                       static_cast<const uint32_t*>(stream_in), dwords, n_cw, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_encode(int r, const void* stream_in, uint64_t n_cw, uint64_t* out, hipStream_t stream)
-{
-    switch (r) {
-    case 3: return launch_encode_r<3>(stream_in, n_cw, out, stream);
-    case 4: return launch_encode_r<4>(stream_in, n_cw, out, stream);
-    case 5: return launch_encode_r<5>(stream_in, n_cw, out, stream);
-    case 6: return launch_encode_r<6>(stream_in, n_cw, out, stream);
-    case 7: return launch_encode_r<7>(stream_in, n_cw, out, stream);
     default: return hipErrorInvalidValue;
     }
 }

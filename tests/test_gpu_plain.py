@@ -178,6 +178,26 @@ def test_encode_parity(gpu_device, r, n_cw):
     assert np.array_equal(out.cpu().numpy().view(np.uint64), ref)
 
 
+@pytest.mark.parametrize("r", [3, 6, 7])
+@pytest.mark.parametrize("n_cw", [1, 2, 65, 4097])
+def test_encode_parity_unaligned_output(gpu_device, r, n_cw):
+    """Output 8-byte but not 16-byte aligned: the encoder takes its 64-bit
+    store form; the words around the output stay untouched."""
+    import torch
+
+    wpc = hm.words_per_codeword(r)
+    stream = synth.message_stream(synth.workload_seed("gpu-enc-unaligned", r, n_cw), n_cw, r)
+    ref = oracle.encode(stream, n_cw, r)
+    buf = torch.full((n_cw * wpc + 2,), 0x5A5A5A5A5A5A5A5A, dtype=torch.int64, device=gpu_device)
+    out = buf[1:1 + n_cw * wpc]
+    assert out.data_ptr() % 16 == 8
+    hm.hamming_encode(to_device(stream, gpu_device), n_cw, r, out)
+    torch.cuda.synchronize()
+    host = buf.cpu().numpy().view(np.uint64)
+    assert np.array_equal(host[1:1 + n_cw * wpc], ref)
+    assert host[0] == 0x5A5A5A5A5A5A5A5A and host[-1] == 0x5A5A5A5A5A5A5A5A
+
+
 def test_tuner_applies_and_persists_valid_shapes(gpu_device, tmp_path):
     import torch
 
