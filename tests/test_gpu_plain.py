@@ -167,7 +167,7 @@ def test_plain_parity_full_size(gpu_device, r, n_cw, p1, p2):
 # ---- encoder -------------------------------------------------------------------
 
 @pytest.mark.parametrize("r", [3, 4, 5, 6, 7])
-@pytest.mark.parametrize("n_cw", [1, 63, 64, 65, 1000, 65537])
+@pytest.mark.parametrize("n_cw", [1, 63, 64, 65, 511, 512, 513, 1000, 1023, 1024, 1025, 65537])
 def test_encode_parity(gpu_device, r, n_cw):
     import torch
 
@@ -196,6 +196,26 @@ def test_encode_parity_unaligned_output(gpu_device, r, n_cw):
     host = buf.cpu().numpy().view(np.uint64)
     assert np.array_equal(host[1:1 + n_cw * wpc], ref)
     assert host[0] == 0x5A5A5A5A5A5A5A5A and host[-1] == 0x5A5A5A5A5A5A5A5A
+
+
+@pytest.mark.parametrize("r,n_cw", [(6, (1 << 24) + 1029), (7, (1 << 23) + 515)])
+def test_encode_parity_grid_loop_sampled(gpu_device, r, n_cw):
+    """Long-message encodes large enough that every workgroup encodes several
+    LDS-staged tiles, with a ragged last tile; slices of the output against
+    the oracle, the input regenerated on the CPU from the same stream."""
+    import torch
+
+    seed = synth.workload_seed("gpu-enc-loop", r)
+    cw = hm.encode(synth.message_stream_torch(seed, n_cw, r, gpu_device), n_cw, r)
+    torch.cuda.synchronize()
+    host = cw.cpu().numpy().view(np.uint64)
+    wpc = hm.words_per_codeword(r)
+    n = 3000
+    rng = np.random.default_rng(n_cw)
+    firsts = [0, 1021, n_cw // 2 + 3, n_cw - n - 7, n_cw - n] + [int(x) for x in rng.integers(0, n_cw - n, 4)]
+    for first in firsts:
+        ref = oracle.encode(synth.message_stream_slice(seed, first, n, r), n, r)
+        assert np.array_equal(host[first * wpc:(first + n) * wpc], ref), first
 
 
 def test_tuner_applies_and_persists_valid_shapes(gpu_device, tmp_path):
