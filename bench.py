@@ -345,6 +345,40 @@ def hamming127_leg(dev, reps: int):
             "frac_hbm": round(algo / med / 1e6 / HBM_PEAK_GBPS, 4)}
 
 
+def errors_leg(dev, reps: int):
+    """Plain decode of 2^26 codewords of r = 4, 5, 6 at single-bit error
+    rates 0, 0.01, 0.1, 0.5 and 1: the correction is branch-free, so the time
+    must not depend on the rate.  One encoded packet per r; each rate applies
+    its own seeded flips to a copy."""
+    import torch
+
+    import paper_1412_6862_amd as hm
+    import synth
+
+    stream = torch.cuda.current_stream()
+    n, rates, rows = 1 << 26, (0.0, 0.01, 0.1, 0.5, 1.0), []
+    for r in WORKLOAD_R:
+        seed = synth.workload_seed("bench-errors", r)
+        clean = hm.encode(synth.message_stream_torch(seed, n, r, dev), n, r)
+        data = torch.empty(hm.hamming_data_bytes(n, r), dtype=torch.uint8, device=dev)
+        ep = torch.empty(n, dtype=torch.uint8, device=dev)
+        algo = algorithmic_bytes_per_codeword(r) * n
+        times = []
+        for p in rates:
+            cw = clean ^ synth.flip_masks_torch(synth.workload_seed("bench-errors", r, str(p)), n, r, p, dev)
+            t = time_events(lambda: hm.hamming_decode(cw, n, r, data, ep, stream), stream, 3, reps)
+            med = t[len(t) // 2]
+            times.append(med)
+            rows.append({"r": r, "p_single": p, "us_p50": round(med * 1e3, 2),
+                         "frac_hbm": round(algo / med / 1e6 / HBM_PEAK_GBPS, 4)})
+            del cw
+        rows.append({"r": r, "max_over_min": round(max(times) / min(times), 4)})
+        del clean, data, ep
+        torch.cuda.empty_cache()
+    return {"workload": "plain decode, 2^26 codewords of r = 4, 5, 6 at single-bit error rates 0, 0.01, 0.1, "
+                        "0.5 and 1", "rows": rows}
+
+
 def host_leg(dev, reps: int):
     """Host-resident Hamming(63,57) packet of 2^26 codewords in pinned memory,
     decoded through the copy pipeline: synchronous transfers (copy in,
@@ -665,9 +699,9 @@ def main() -> int:
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner before timing instead of loading the committed shapes")
     ap.add_argument("--seg-packets", type=int, default=1 << 19)
-    ap.add_argument("--legs", default="latency,sizes,r7,batch,serve,host,seg,planes,encode",
+    ap.add_argument("--legs", default="latency,sizes,r7,errors,batch,serve,host,seg,planes,encode",
                     help="extra legs after the plain one (which gives the reported value): "
-                         "comma-separated subset of latency,sizes,r7,batch,serve,host,seg,planes,encode, or none")
+                         "comma-separated subset of latency,sizes,r7,errors,batch,serve,host,seg,planes,encode, or none")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (counter calibration)")
     args = ap.parse_args()
@@ -799,6 +833,8 @@ def main() -> int:
         out["size_sweep"] = sizes_leg(dev)
     if "r7" in legs:
         out["hamming127"] = hamming127_leg(dev, 20)
+    if "errors" in legs:
+        out["error_rates"] = errors_leg(dev, 20)
     if "batch" in legs:
         out["batched"] = batched_leg(dev, args.batch_packets, 5)
     if "serve" in legs:
