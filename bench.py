@@ -221,7 +221,7 @@ def batched_leg(dev, n_packets: int, reps: int):
     }
 
 
-def serving_leg(dev, plain_gBps_per_r: dict, loads, n_requests: int, warm: int):
+def serving_leg(dev, plain_gBps_per_r: dict, loads, n_requests: int, warm: int, batch_log2: int = 24):
     """Open-loop serving: Poisson arrivals from 256 simulated SDR streams
     (stream s decodes code r = 4 + s % 4), request sizes log-uniform in
     [256, 2^18] codewords, 10% single-bit errors, offered load swept as a
@@ -266,7 +266,7 @@ def serving_leg(dev, plain_gBps_per_r: dict, loads, n_requests: int, warm: int):
     t_plain = nbytes / np.array([plain_gBps_per_r[int(x)] for x in r]) / 1e9
     # at most 2^24 codewords per batch: larger batches keep the slots busy longer at high load
     # (2^26: p50 at 70% load 265-279 us against 163-177 us), smaller ones cost throughput
-    srv = hm.Server(pool, slots=4, max_batch_packets=4096, max_batch_codewords=1 << 24,
+    srv = hm.Server(pool, slots=4, max_batch_packets=4096, max_batch_codewords=1 << batch_log2,
                     output_pool_bytes=32 << 30, auto_release=True)
     out = []
     try:
@@ -292,8 +292,9 @@ def serving_leg(dev, plain_gBps_per_r: dict, loads, n_requests: int, warm: int):
         del pool
         torch.cuda.empty_cache()
     return {"workload": "256 SDR streams, r = 4 + stream % 4, request sizes log-uniform in [256, 2^18] "
-                        "codewords, 10% single-bit errors, Poisson arrivals; 4 batches in flight of at most 2^24 "
-                        "codewords; output pool (device-memory admission cap) 32 GiB", "points": out}
+                        "codewords, 10% single-bit errors, Poisson arrivals; 4 batches in flight of at most 2^"
+                        + str(batch_log2) + " codewords; output pool (device-memory admission cap) 32 GiB",
+            "points": out}
 
 
 def latency_leg(dev, reps: int):
@@ -696,6 +697,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--batch-packets", type=int, default=20000)
     ap.add_argument("--serve-requests", type=int, default=100000)
+    ap.add_argument("--serve-batch-log2", type=int, default=24, choices=range(16, 31), metavar="L",
+                    help="serving leg: at most 2^L codewords per batch")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner before timing instead of loading the committed shapes")
     ap.add_argument("--seg-packets", type=int, default=1 << 19)
@@ -841,7 +844,7 @@ def main() -> int:
         gBps = {x["r"]: x["algorithmic_GBps"] for x in per_r}
         gBps.setdefault(7, gBps[DOMINANT_R])
         out["serving"] = serving_leg(dev, gBps, (0.1, 0.3, 0.5, 0.7, 0.8, 0.9), args.serve_requests,
-                                     max(200, args.serve_requests // 10))
+                                     max(200, args.serve_requests // 10), args.serve_batch_log2)
     if "host" in legs:
         out["host_pipeline"] = host_leg(dev, 3)
     if "planes" in legs:
