@@ -221,7 +221,7 @@ def batched_leg(dev, n_packets: int, reps: int):
     }
 
 
-def serving_leg(dev, plain_gBps_per_r: dict, loads, n_requests: int, warm: int, batch_log2: int = 24):
+def serving_leg(dev, plain_gBps_per_r: dict, loads, n_requests: int, warm: int, batch_log2: int = 25):
     """Open-loop serving: Poisson arrivals from 256 simulated SDR streams
     (stream s decodes code r = 4 + s % 4), request sizes log-uniform in
     [256, 2^18] codewords, 10% single-bit errors, offered load swept as a
@@ -264,8 +264,9 @@ def serving_leg(dev, plain_gBps_per_r: dict, loads, n_requests: int, warm: int, 
     # bandwidth on its r; the offered load is rho over the mean of these
     nbytes = np.array([float(n) * algorithmic_bytes_per_codeword(int(x)) for n, x in zip(sizes, r)])
     t_plain = nbytes / np.array([plain_gBps_per_r[int(x)] for x in r]) / 1e9
-    # at most 2^24 codewords per batch: larger batches keep the slots busy longer at high load
-    # (2^26: p50 at 70% load 265-279 us against 163-177 us), smaller ones cost throughput
+    # at most 2^25 codewords per batch (the default): over caps 2^24, 2^25 and 2^26, each run twice
+    # alone and twice after the batched leg, 2^25 had the lowest or equal p50 at 70-80% load and
+    # kept 15-16 Tbit/s at 90%; 2^24 fell to 13.7 Tbit/s after the batched leg, 2^26 doubled p50 at 80%
     srv = hm.Server(pool, slots=4, max_batch_packets=4096, max_batch_codewords=1 << batch_log2,
                     output_pool_bytes=32 << 30, auto_release=True)
     out = []
@@ -697,7 +698,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--batch-packets", type=int, default=20000)
     ap.add_argument("--serve-requests", type=int, default=100000)
-    ap.add_argument("--serve-batch-log2", type=int, default=24, choices=range(16, 31), metavar="L",
+    ap.add_argument("--serve-batch-log2", type=int, default=25, choices=range(16, 31), metavar="L",
                     help="serving leg: at most 2^L codewords per batch")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner before timing instead of loading the committed shapes")
