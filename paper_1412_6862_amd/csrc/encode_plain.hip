@@ -95,8 +95,10 @@ __global__ __launch_bounds__(256) void encode_plain_kernel(const uint32_t* __res
 // thread, 256 apart, so stores stay coalesced).  The tile's slice of the
 // message stream is staged in LDS with coalesced 64-bit loads; each thread
 // then funnel-shifts its messages out of LDS instead of issuing PW+1 32-bit
-// loads per codeword at a k-bit stride.  Words past the end of the stream are
-// staged as zero (their bits are masked off or belong to no codeword).
+// loads per codeword at a k-bit stride.  A workgroup loops over tiles and
+// loads the next tile's words into registers while it encodes the current
+// one.  Words past the end of the stream are staged as zero (their bits are
+// masked off or belong to no codeword).
 template <int R>
 __global__ __launch_bounds__(256) void encode_staged_kernel(const uint64_t* __restrict__ stream, uint64_t stream_q,
                                                             uint64_t n_cw, uint64_t* __restrict__ cw_out,
@@ -105,18 +107,33 @@ __global__ __launch_bounds__(256) void encode_staged_kernel(const uint64_t* __re
     using C = Code<R>;
     using S = EncShape<R>;
     constexpr int PER = S::PER;
+    constexpr uint32_t LPT = (S::LDS_Q + 255) / 256;      // staged words per thread
     __shared__ uint64_t lds_q[S::LDS_Q];
     const uint32_t* lds = reinterpret_cast<const uint32_t*>(lds_q);
     const uint64_t n_tiles = (n_cw + S::CW - 1) / S::CW;
     const uint64_t n_vec = (n_cw + PER - 1) / PER;
-    for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    uint64_t nxt[LPT];
+    auto fetch = [&](uint64_t t) {
+        const uint64_t q0 = (t * S::CW * C::K) >> 6;
+#pragma unroll
+        for (uint32_t l = 0; l < LPT; ++l) {
+            const uint32_t e = threadIdx.x + 256u * l;
+            const uint64_t q = q0 + e;
+            nxt[l] = (e < S::LDS_Q && q < stream_q) ? __builtin_nontemporal_load(stream + q) : uint64_t(0);
+        }
+    };
+    uint64_t t = blockIdx.x;
+    if (t < n_tiles) fetch(t);
+    for (; t < n_tiles; t += gridDim.x) {
         const uint64_t q0 = (t * S::CW * C::K) >> 6;      // first staged word
         __syncthreads();                                   // the previous tile's reads are done
-        for (uint32_t e = threadIdx.x; e < S::LDS_Q; e += 256) {
-            const uint64_t q = q0 + e;
-            lds_q[e] = q < stream_q ? __builtin_nontemporal_load(stream + q) : uint64_t(0);
+#pragma unroll
+        for (uint32_t l = 0; l < LPT; ++l) {
+            const uint32_t e = threadIdx.x + 256u * l;
+            if (e < S::LDS_Q) lds_q[e] = nxt[l];
         }
         __syncthreads();
+        if (t + gridDim.x < n_tiles) fetch(t + gridDim.x);   // next tile's words load during this tile's work
 #pragma unroll
         for (uint32_t w = 0; w < S::VPT; ++w) {
             const uint64_t j = (t * S::VPT + w) * 256 + threadIdx.x;
@@ -125,7 +142,6 @@ __global__ __launch_bounds__(256) void encode_staged_kernel(const uint64_t* __re
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
                 const uint64_t o = (j * PER + u) * C::K;
-                // (o >> 5) - 2*q0 + PW < 2*LDS_Q for every codeword of the tile
                 const uint32_t* src = lds + uint32_t((o >> 5) - 2 * q0);
                 uint32_t raw[C::PW + 1];
 #pragma unroll
@@ -137,9 +153,12 @@ __global__ __launch_bounds__(256) void encode_staged_kernel(const uint64_t* __re
     }
 }
 
-// Workgroup cap of one staged launch (four times this for the direct kernel);
-// larger inputs loop.  A few tiles per workgroup measured faster than one.
-constexpr uint64_t kEncodeMaxBlocks = 16384;
+// Workgroup caps of one launch; larger inputs loop.  The staged kernel's
+// prefetch needs a few tiles per workgroup: 2^15 workgroups (2 tiles each for
+// 2^26 codewords of r = 6) measured faster than one tile per workgroup, and
+// than 2^12-2^14 workgroups.
+constexpr uint64_t kEncodeMaxBlocks = 32768;
+constexpr uint64_t kEncodeDirectMaxBlocks = 65536;
 
 template <int R>
 static hipError_t launch_encode_r(const void* stream_in, uint64_t n_cw, uint64_t* out, hipStream_t stream)
@@ -157,7 +176,7 @@ static hipError_t launch_encode_r(const void* stream_in, uint64_t n_cw, uint64_t
     } else {
         constexpr uint64_t per = EncShape<R>::PER;
         uint64_t blocks = ((n_cw + per - 1) / per + 255) / 256;
-        if (blocks > 4 * kEncodeMaxBlocks) blocks = 4 * kEncodeMaxBlocks;
+        if (blocks > kEncodeDirectMaxBlocks) blocks = kEncodeDirectMaxBlocks;
         if (blocks == 0) return hipSuccess;
         hipLaunchKernelGGL((encode_plain_kernel<R>), dim3(uint32_t(blocks)), dim3(256), 0, stream,
                            static_cast<const uint32_t*>(stream_in), 2 * stream_q, n_cw, out, out16);
