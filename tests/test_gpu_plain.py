@@ -198,11 +198,14 @@ def test_encode_parity_unaligned_output(gpu_device, r, n_cw):
     assert host[0] == 0x5A5A5A5A5A5A5A5A and host[-1] == 0x5A5A5A5A5A5A5A5A
 
 
-@pytest.mark.parametrize("r,n_cw", [(6, (1 << 24) + 1029), (7, (1 << 23) + 515)])
+# 2^15 workgroups of 1,024 (r = 6) or 512 (r = 7) codewords, plus a few more
+# tiles: the first workgroups loop, prefetching a second tile, the last of
+# them ragged.
+@pytest.mark.parametrize("r,n_cw", [(6, (1 << 25) + 3 * 1024 + 29), (7, (1 << 24) + 2 * 512 + 3)])
 def test_encode_parity_grid_loop_sampled(gpu_device, r, n_cw):
-    """Long-message encodes large enough that every workgroup encodes several
-    LDS-staged tiles, with a ragged last tile; slices of the output against
-    the oracle, the input regenerated on the CPU from the same stream."""
+    """Long-message encodes with more LDS-staged tiles than workgroups and a
+    ragged last tile; slices of the output against the oracle, the input
+    regenerated on the CPU from the same stream."""
     import torch
 
     seed = synth.workload_seed("gpu-enc-loop", r)
@@ -213,6 +216,9 @@ def test_encode_parity_grid_loop_sampled(gpu_device, r, n_cw):
     n = 3000
     rng = np.random.default_rng(n_cw)
     firsts = [0, 1021, n_cw // 2 + 3, n_cw - n - 7, n_cw - n] + [int(x) for x in rng.integers(0, n_cw - n, 4)]
+    # the tiles the first workgroups take second
+    tile = 1024 if r == 6 else 512
+    firsts += [min(f, n_cw - n) for f in ((1 << 15) * tile - 17, (1 << 15) * tile + 100)]
     for first in firsts:
         ref = oracle.encode(synth.message_stream_slice(seed, first, n, r), n, r)
         assert np.array_equal(host[first * wpc:(first + n) * wpc], ref), first
