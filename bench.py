@@ -29,6 +29,10 @@ P_SINGLE = 0.1
 DOMINANT_R = 6
 PROFILE_GLOB = os.path.join(ROOT, "profiles", "decode_plain_r6_2p26_traffic.md")
 TUNED_SHAPES = os.path.join(ROOT, "paper_1412_6862_amd", "tuned_shapes.json")
+SERVE_LOADS = (0.1, 0.3, 0.5, 0.7, 0.8, 0.9)
+SERVE_REPORT_LOAD = 0.9
+# the last stdout line is the record a reader keeps; it must stay short
+SUMMARY_MAX_BYTES = 4096
 
 
 def algorithmic_bytes_per_codeword(r: int) -> float:
@@ -264,6 +268,8 @@ def serving_leg(dev, plain_gBps_per_r: dict, loads, n_requests: int, warm: int, 
     # bandwidth on its r; the offered load is rho over the mean of these
     nbytes = np.array([float(n) * algorithmic_bytes_per_codeword(int(x)) for n, x in zip(sizes, r)])
     t_plain = nbytes / np.array([plain_gBps_per_r[int(x)] for x in r]) / 1e9
+    # the plain decoder's rate on this mix: every request decoded by a plain call at its r's measured bandwidth
+    plain_mix_Gbps = float(bits.sum()) / float(t_plain.sum()) / 1e9
     # at most 2^25 codewords per batch (the default): over caps 2^24, 2^25 and 2^26, each run twice
     # alone and twice after the batched leg, 2^25 had the lowest or equal p50 at 70-80% load and
     # kept 15-16 Tbit/s at 90%; 2^24 fell to 13.7 Tbit/s after the batched leg, 2^26 doubled p50 at 80%
@@ -287,7 +293,13 @@ def serving_leg(dev, plain_gBps_per_r: dict, loads, n_requests: int, warm: int, 
                 "p99_us": round(float(lat_us[int(0.99 * (len(lat_us) - 1))]), 1),
                 "offered_Gbps": round(float(bits[warm:].sum()) / span_s / 1e9, 1),
                 "achieved_Gbps": round(float(bits[warm:].sum()) / window_s / 1e9, 1),
+                "served_over_plain": round(float(bits[warm:].sum()) / window_s / 1e9 / plain_mix_Gbps, 4),
             })
+        # saturation: every request queued at time 0, drained as fast as the server can
+        lat, elapsed = srv.run_trace(np.zeros(total, dtype=np.uint64), offs, sizes, r, timeout_s=120)
+        sat_Gbps = float(bits.sum()) / (elapsed / 1e9) / 1e9
+        saturated = {"requests": total, "elapsed_ms": round(elapsed / 1e6, 2), "achieved_Gbps": round(sat_Gbps, 1),
+                     "served_over_plain": round(sat_Gbps / plain_mix_Gbps, 4)}
     finally:
         srv.close()
         del pool
@@ -295,7 +307,7 @@ def serving_leg(dev, plain_gBps_per_r: dict, loads, n_requests: int, warm: int, 
     return {"workload": "256 SDR streams, r = 4 + stream % 4, request sizes log-uniform in [256, 2^18] "
                         "codewords, 10% single-bit errors, Poisson arrivals; 4 batches in flight of at most 2^"
                         + str(batch_log2) + " codewords; output pool (device-memory admission cap) 32 GiB",
-            "points": out}
+            "plain_mix_Gbps": round(plain_mix_Gbps, 1), "points": out, "saturated": saturated}
 
 
 def latency_leg(dev, reps: int):
@@ -457,7 +469,7 @@ def sizes_leg(dev):
         data = torch.empty(hm.hamming_data_bytes(nmax, r), dtype=torch.uint8, device=dev)
         ep = torch.empty(nmax, dtype=torch.uint8, device=dev)
         k = hm.hamming_message_bits(r)
-        for lg in range(10, 29, 2):
+        for lg in range(10, 29):
             n = 1 << lg
             reps = 200 if lg <= 20 else 20
             t = time_events(lambda: hm.hamming_decode(cw, n, r, data, ep, stream), stream, 3, reps)
@@ -469,7 +481,7 @@ def sizes_leg(dev):
                          "cache_resident": algo < 256e6})
         del cw, data, ep
         torch.cuda.empty_cache()
-    return {"workload": "plain decode, packet sizes 2^10..2^28 codewords (every 4x) of r = 4, 5, 6, "
+    return {"workload": "plain decode, packet sizes 2^10..2^28 codewords (every power of two) of r = 4, 5, 6, "
                         "10% single-bit errors", "rows": rows}
 
 
@@ -551,7 +563,7 @@ def segmented_encode_bytes(msg_bytes: int, t: int) -> float:
     return 32 + msg_bytes + bits / 8.0
 
 
-def segmented_leg(dev, n_packets: int, reps: int, lat_reps: int):
+def segmented_leg(dev, n_packets: int, reps: int, lat_reps: int, shapes=None):
     """The paper's packets (Sec. II, Table 1 grid): M bytes in t shortened
     segments.  Per shape: a batch of n_packets packets encoded on the GPU in
     one launch (the transmitter half, timed too), flips from the seeded
@@ -565,7 +577,7 @@ def segmented_leg(dev, n_packets: int, reps: int, lat_reps: int):
 
     stream = torch.cuda.current_stream()
     rows = []
-    for mb, t in SEG_SHAPES:
+    for mb, t in (shapes or SEG_SHAPES):
         b = hm.SegmentedBatch(n_packets, mb, t, device=dev)
         seed = synth.workload_seed("bench-seg", mb, t)
         b.msg.copy_(synth.draws_torch(seed, 0, n_packets * b.msg_stride, dev))
@@ -640,6 +652,38 @@ def copy_ceiling(dev) -> float:
     return round(2 * (1 << 30) / t[len(t) // 2] / 1e6, 1)
 
 
+def host_cpu_info() -> dict:
+    """CPU model, SMT state and the CPUs this process may run on."""
+    info = {"cpu_model": "unknown", "smt": "unknown", "cpus_allowed": None, "host_cpus": os.cpu_count()}
+    try:
+        siblings = cores = None
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                key, _, val = line.partition(":")
+                key = key.strip()
+                if key == "model name" and info["cpu_model"] == "unknown":
+                    info["cpu_model"] = val.strip()
+                elif key == "siblings" and siblings is None:
+                    siblings = int(val)
+                elif key == "cpu cores" and cores is None:
+                    cores = int(val)
+        if siblings and cores:
+            info["threads_per_core"] = siblings // cores
+    except (OSError, ValueError):
+        pass
+    try:
+        with open("/sys/devices/system/cpu/smt/active") as fh:
+            info["smt"] = "on" if fh.read().strip() == "1" else "off"
+    except OSError:
+        if info.get("threads_per_core"):
+            info["smt"] = "on" if info["threads_per_core"] > 1 else "off"
+    try:
+        info["cpus_allowed"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    return info
+
+
 def cpu_baseline(log2_sample: int):
     """The oracle on the host cores over a slice of the same workload."""
     import oracle
@@ -649,6 +693,7 @@ def cpu_baseline(log2_sample: int):
     threads = oracle.default_threads()
     bits = 0
     elapsed = 0.0
+    single = None
     for r in WORKLOAD_R:
         seed = synth.workload_seed("bench", r, str(P_SINGLE))
         stream = synth.message_stream(seed, n, r)
@@ -665,27 +710,73 @@ def cpu_baseline(log2_sample: int):
             t0 = time.perf_counter()
             oracle.decode(y[:m], r, nthreads=1)
             single = m * ((1 << r) - 1 - r) / (time.perf_counter() - t0) / 1e9
-    model = "unknown"
-    try:
-        with open("/proc/cpuinfo") as fh:
-            for line in fh:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
-    return {
+    out = {
         "value": round(bits / elapsed / 1e9, 3),
         "unit": "Gbit/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": "2^%d codewords of each of r=4,5,6 (p=%.2f), %d threads, decode only, %.2f s"
-                  % (log2_sample, P_SINGLE, threads, elapsed),
+        "sample": "2^%d codewords of each of r=4,5,6 (p=%.2f), %d threads, decode only, %.2f s; one thread "
+                  "on a 2^22-codeword slice of r=6" % (log2_sample, P_SINGLE, threads, elapsed),
         "single_thread_Gbps_r6": round(single, 3),
-        "cpu_model": model,
-        "host_cpus": os.cpu_count(),
-        "segmented_us_per_packet_1thread": cpu_segmented(100),
     }
+    out.update(host_cpu_info())
+    out["segmented_us_per_packet_1thread"] = cpu_segmented(100)
+    return out
+
+
+PAPER_SPEEDUP_CONTEXT = ("99x: GTX 560 over one core of a 4-core 3.4 GHz Intel (Sec. IV, abstract); other "
+                         "hardware and a latency-bound packet size, context only")
+
+
+def _pick(d: dict, *keys):
+    return {k: d[k] for k in keys if k in d}
+
+
+def summary_line(out: dict) -> dict:
+    """The compact final line: the headline keys, the dominant kernel's
+    roofline, the CPU baseline and one figure per extra leg.  The per-leg
+    detail travels on the earlier lines (and in the --detail file)."""
+    s = _pick(out, "metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+              "scaling", "vs_baseline", "dtype", "data", "config")
+    s["roofline"] = _pick(out["roofline"], "kernel", "bound", "achieved", "peak", "unit", "frac", "traffic",
+                          "algorithmic_bytes_per_launch", "avg_launch_us", "min_launch_us", "max_launch_us")
+    s["plain_frac_hbm"] = {str(x["r"]): x["frac_hbm"] for x in out.get("per_r", [])}
+    if "batched" in out:
+        b = out["batched"]
+        s["batched"] = _pick(b, "ms_p50", "payload_Gbps", "frac_hbm", "batched_over_plain")
+    if "serving" in out:
+        pts = out["serving"]["points"]
+        at = [p for p in pts if p["offered_load"] == SERVE_REPORT_LOAD]
+        s["serving"] = {"offered_load": SERVE_REPORT_LOAD}
+        if at:
+            s["serving"].update(_pick(at[0], "p50_us", "p99_us", "achieved_Gbps", "served_over_plain"))
+        sat = out["serving"].get("saturated")
+        if sat:
+            s["serving"]["capacity_over_plain"] = sat["served_over_plain"]
+        s["serving"]["points"] = [[p["offered_load"], p["p50_us"], p["p99_us"], p["achieved_Gbps"]] for p in pts]
+    if "hamming127" in out:
+        s["hamming127"] = _pick(out["hamming127"], "us_p50", "frac_hbm")
+    if "latency_hamming74" in out:
+        s["hamming74_launch"] = _pick(out["latency_hamming74"], "p50_us", "p99_us")
+    if "cpu_baseline" in out:
+        cb = out["cpu_baseline"]
+        s["cpu_baseline"] = _pick(cb, "value", "unit", "cores", "kind", "sample", "cpu_model", "smt",
+                                  "cpus_allowed", "single_thread_Gbps_r6", "gpu_over_oracle")
+        s["cpu_baseline"]["paper_speedup_context"] = PAPER_SPEEDUP_CONTEXT
+    s["legs"] = sorted(k for k in out if k not in s and k not in ("per_r", "tuned_shapes"))
+    # over the limit (never expected): shed the least important fields first
+    for path in (("serving", "points"), ("cpu_baseline", "sample"), ("config", "workload"), ("legs",)):
+        if len(json.dumps(s, separators=(",", ":"))) <= SUMMARY_MAX_BYTES:
+            break
+        d = s
+        for p in path[:-1]:
+            d = d.get(p, {})
+        d.pop(path[-1], None)
+    return s
+
+
+def emit(obj: dict) -> None:
+    print(json.dumps(obj, separators=(",", ":")), flush=True)
 
 
 def main() -> int:
@@ -703,9 +794,12 @@ def main() -> int:
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner before timing instead of loading the committed shapes")
     ap.add_argument("--seg-packets", type=int, default=1 << 19)
+    ap.add_argument("--seg-shapes", default="",
+                    help="segmented leg: comma-separated M/t shapes (e.g. 1200/4); default the Table 1 grid")
     ap.add_argument("--legs", default="latency,sizes,r7,errors,batch,serve,host,seg,planes,encode",
                     help="extra legs after the plain one (which gives the reported value): "
                          "comma-separated subset of latency,sizes,r7,errors,batch,serve,host,seg,planes,encode, or none")
+    ap.add_argument("--detail", default="", metavar="PATH", help="also write every leg's full result to PATH (JSON)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (counter calibration)")
     args = ap.parse_args()
@@ -785,6 +879,7 @@ def main() -> int:
             "r": r, "n_cw": n_cw, "avg_us": round(avg * 1e3, 2),
             "p50_us": round(times[len(times) // 2] * 1e3, 2),
             "p99_us": round(times[min(len(times) - 1, int(0.99 * len(times)))] * 1e3, 2),
+            "min_us": round(times[0] * 1e3, 2), "max_us": round(times[-1] * 1e3, 2),
             "algorithmic_GBps": round(algo / avg / 1e6, 1),
             "frac_hbm": round(algo / avg / 1e6 / HBM_PEAK_GBPS, 4),
             "payload_Gbps": round(n_cw * k / avg / 1e6, 1),
@@ -824,37 +919,52 @@ def main() -> int:
             "traffic": traffic,
             "algorithmic_bytes_per_launch": int(algorithmic_bytes_per_codeword(DOMINANT_R) * n_cw),
             "avg_launch_us": dom["avg_us"],
+            "min_launch_us": dom["min_us"],
+            "max_launch_us": dom["max_us"],
             "runtime_d2d_copy_GBps": copy_ceiling(dev),
         },
         "per_r": per_r,
         "tuned_shapes": tuned,
     }
+    emit({"leg": "plain", "per_r": per_r, "roofline": out["roofline"], "tuned_shapes": tuned})
     del packets
     torch.cuda.empty_cache()
+
+    def run_leg(key, fn, *a):
+        t0 = time.perf_counter()
+        out[key] = fn(*a)
+        emit({"leg": key, "elapsed_s": round(time.perf_counter() - t0, 1), **out[key]})
+
     if "latency" in legs:
-        out["latency_hamming74"] = latency_leg(dev, 1000)
+        run_leg("latency_hamming74", latency_leg, dev, 1000)
     if "sizes" in legs:
-        out["size_sweep"] = sizes_leg(dev)
+        run_leg("size_sweep", sizes_leg, dev)
     if "r7" in legs:
-        out["hamming127"] = hamming127_leg(dev, 20)
+        run_leg("hamming127", hamming127_leg, dev, 20)
     if "errors" in legs:
-        out["error_rates"] = errors_leg(dev, 20)
+        run_leg("error_rates", errors_leg, dev, 20)
     if "batch" in legs:
-        out["batched"] = batched_leg(dev, args.batch_packets, 5)
+        run_leg("batched", batched_leg, dev, args.batch_packets, 5)
     if "serve" in legs:
         gBps = {x["r"]: x["algorithmic_GBps"] for x in per_r}
+        if "hamming127" in out:
+            gBps[7] = out["hamming127"]["frac_hbm"] * HBM_PEAK_GBPS
         gBps.setdefault(7, gBps[DOMINANT_R])
-        out["serving"] = serving_leg(dev, gBps, (0.1, 0.3, 0.5, 0.7, 0.8, 0.9), args.serve_requests,
-                                     max(200, args.serve_requests // 10), args.serve_batch_log2)
+        run_leg("serving", serving_leg, dev, gBps, SERVE_LOADS, args.serve_requests,
+                max(200, args.serve_requests // 10), args.serve_batch_log2)
     if "host" in legs:
-        out["host_pipeline"] = host_leg(dev, 3)
+        run_leg("host_pipeline", host_leg, dev, 3)
     if "planes" in legs:
-        out["planes"] = planes_leg(dev, 10)
+        run_leg("planes", planes_leg, dev, 10)
     if "encode" in legs:
-        out["encode"] = encode_leg(dev, 10)
+        run_leg("encode", encode_leg, dev, 10)
     if "seg" in legs:
-        out["segmented"] = segmented_leg(dev, args.seg_packets, 5, 200)
+        shapes = SEG_SHAPES
+        if args.seg_shapes:
+            shapes = [tuple(int(v) for v in s.split("/")) for s in args.seg_shapes.split(",")]
+        run_leg("segmented", segmented_leg, dev, args.seg_packets, 5, 200, shapes)
     if not args.no_cpu:
+        t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(args.cpu_log2)
         cb = out["cpu_baseline"]
         cb["gpu_over_oracle"] = {
@@ -863,11 +973,16 @@ def main() -> int:
         if "segmented" in out:
             cpu = out["cpu_baseline"]["segmented_us_per_packet_1thread"]
             for row in out["segmented"]["shapes"]:
-                c = cpu["%d/%d" % (row["M"], row["t"])]
-                row["speedup_vs_oracle_1thread"] = {
-                    "single_packet": round(c / row["single_packet_p50_us"], 1),
-                    "batched": round(c / row["us_per_packet_batched"], 0)}
-    print(json.dumps(out), flush=True)
+                c = cpu.get("%d/%d" % (row["M"], row["t"]))
+                if c:
+                    row["speedup_vs_oracle_1thread"] = {
+                        "single_packet": round(c / row["single_packet_p50_us"], 1),
+                        "batched": round(c / row["us_per_packet_batched"], 0)}
+        emit({"leg": "cpu_baseline", "elapsed_s": round(time.perf_counter() - t0, 1), **cb})
+    if args.detail:
+        with open(args.detail, "w") as fh:
+            json.dump(out, fh, indent=1)
+    emit(summary_line(out))
     return 0
 
 

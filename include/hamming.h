@@ -120,6 +120,14 @@ int hamming_encode(const void *data_in, uint64_t n_cw, int r,
 int hamming_plain_config_set(int r, int lane_codewords, uint64_t max_blocks, uint32_t xcd_chunk);
 int hamming_plain_config_get(int r, int *lane_codewords, uint64_t *max_blocks, uint32_t *xcd_chunk);
 
+/* Workgroups (of 256 work-items) that hamming_decode would launch for n_cw
+ * codewords of code r under the current launch shape: one wave per tile of
+ * 64*lane_codewords codewords, capped by max_blocks and by the 2^32-1
+ * work-items a dispatch can hold; waves loop over the tiles beyond the grid.
+ * Host-only and informative (tests, capacity planning); 0 for an invalid r,
+ * n_cw = 0 or n_cw above HAMMING_MAX_CODEWORDS. */
+uint64_t hamming_decode_grid(uint64_t n_cw, int r);
+
 /* ---- batched decode ------------------------------------------------------ */
 
 /*
@@ -161,10 +169,19 @@ typedef struct hamming_packet {
 int hamming_batch_layout(hamming_packet *descs, uint32_t n, uint64_t *data_words,
                          uint64_t *errpos_bytes);
 
-/* Device workspace bytes hamming_decode_batch needs for max_packets packets
- * (tile prefix sums and the tile-to-packet map); 0 if max_packets >
- * HAMMING_MAX_BATCH. */
+/* Recommended device workspace bytes of hamming_decode_batch for max_packets
+ * packets: batch totals, tile prefix sums, a coarse tile-to-packet map and a
+ * fine map with one entry per tile of any batch of up to
+ * max(2^24, 4*max_packets) tiles.  0 if max_packets > HAMMING_MAX_BATCH. */
 uint64_t hamming_batch_workspace_bytes(uint32_t max_packets);
+
+/* Smallest workspace hamming_decode_batch accepts for max_packets packets (a
+ * fine map of one entry).  Any size from this one up works: a fine map with
+ * fewer entries than the batch has tiles groups 2^g tiles per entry, and each
+ * wave then finds its tile's packet by probing the prefix sums 64 entries at
+ * a time from the entry's packet on (slower, same results).  0 if max_packets
+ * > HAMMING_MAX_BATCH. */
+uint64_t hamming_batch_workspace_min_bytes(uint32_t max_packets);
 
 /*
  * Batched decode: decode every packet of a device-resident descriptor array.
@@ -196,8 +213,13 @@ uint64_t hamming_batch_workspace_bytes(uint32_t max_packets);
  *                            rejected packet is skipped; the others decode as
  *                            usual.
  *   workspace, workspace_bytes : device scratch, 8-byte aligned, at least
- *                            hamming_batch_workspace_bytes(max_packets); owned
- *                            by the caller, not shared by concurrent calls.
+ *                            hamming_batch_workspace_min_bytes(max_packets)
+ *                            (hamming_batch_workspace_bytes(max_packets) for the
+ *                            exact map); owned by the caller, not shared by
+ *                            concurrent calls.  Its first 64 bytes receive the
+ *                            batch totals: tiles (uint64), packets (uint64),
+ *                            then the log2 group sizes of the coarse and fine
+ *                            maps (two uint32).
  * Returns HAMMING_OK, HAMMING_EINVAL, HAMMING_EALIGN, HAMMING_ERANGE,
  * HAMMING_ENOMEM (workspace too small) or HAMMING_EDEVICE.
  */
@@ -220,6 +242,21 @@ int hamming_decode_batch(const uint64_t *cw_arena, uint64_t cw_words,
 int hamming_batch_config_set(int schedule, uint32_t xcd_chunk, uint32_t grid_cap_blocks, int use_graph);
 int hamming_batch_config_get(int *schedule, uint32_t *xcd_chunk, uint32_t *grid_cap_blocks, int *use_graph);
 
+/* Workgroups of the batched decode kernel for these arguments of
+ * hamming_decode_batch: one wave per tile of the largest batch they allow
+ * (min(cw_words/256, max_codewords/128) + max_packets tiles; max_codewords 0 =
+ * no hint), capped by grid_cap_blocks and by the 2^32-1 work-items a dispatch
+ * can hold.  Host-only and informative; 0 if max_packets is 0 or above
+ * HAMMING_MAX_BATCH. */
+uint64_t hamming_decode_batch_grid(uint64_t cw_words, uint32_t max_packets, uint64_t max_codewords);
+
+/* Destroy the hipGraph executables hamming_decode_batch has cached (they
+ * otherwise live until the process ends): waits for each cached graph's
+ * device to go idle, then frees them; later calls capture afresh.  Must not
+ * run while another thread is inside hamming_decode_batch.  Returns
+ * HAMMING_OK or HAMMING_EDEVICE. */
+int hamming_batch_release_graphs(void);
+
 /* ---- bit-plane input layout -------------------------------------------------
  *
  * The index-set clustering of Sec. III.A (Fig. 4) carried to single
@@ -236,7 +273,8 @@ int hamming_batch_config_get(int *schedule, uint32_t *xcd_chunk, uint32_t *grid_
 uint64_t hamming_planes_words(uint64_t n_cw, int r);
 
 /*
- * Decode n_cw codewords given in the plane layout.
+ * Decode n_cw codewords given in the plane layout (n_cw at most
+ * 2^37 - 2^13 per call, the reach of one launch).
  *   planes     : device, n planes of plane_words 64-bit words (8-byte aligned).
  *   data_out   : device, hamming_data_bytes(n_cw, r) bytes (8-byte aligned;
  *                16-byte alignment enables vector stores).
@@ -414,8 +452,12 @@ int hamming_tune_load(const char *cache_path);
  * batch slots is free, so requests that arrive while earlier batches run are
  * admitted and overlap with them on the device.  A batch of at most 16
  * requests and 2^20 codewords is one decode launch with its descriptors in
- * the kernel arguments; a larger one is one hamming_decode_batch call.  A request is admitted when its outputs fit in the server's output
- * pool (the device-memory admission cap); until then it waits in FIFO order.
+ * the kernel arguments.  A larger one is planned on the host, which validated
+ * every request at submission: the tile prefix sums and a coarse
+ * tile-to-packet map go to the device with the descriptors in one copy, and
+ * one decode launch follows (no planning or map kernels).  A request is
+ * admitted when its outputs fit in the server's output pool (the
+ * device-memory admission cap); until then it waits in FIFO order.
  * The server is driven by the caller (hamming_server_progress) and keeps no
  * thread of its own; one server must not be used from two threads at once.
  * The arithmetic of every request is exactly the plain decode's.
@@ -436,7 +478,7 @@ typedef struct hamming_completion {
     uint64_t errpos_offset;       /* byte offset of the errpos bytes in the output pool */
     uint64_t submit_ns;           /* arrival time given to hamming_server_submit */
     uint64_t complete_ns;         /* time the server observed the batch complete */
-    int32_t status;               /* HAMMING_OK or the descriptor's error status */
+    int32_t status;               /* HAMMING_OK, or the error of the launch of the request's batch */
     uint32_t reserved;
 } hamming_completion;
 
@@ -476,7 +518,9 @@ int hamming_server_submit(hamming_server *server, uint64_t in_word_off, uint64_t
  * Non-blocking step: record completions of finished batches (freeing outputs
  * when auto_release is set), admit waiting requests in FIFO order while their
  * outputs fit, and launch one batch per free slot.  Returns HAMMING_OK or
- * HAMMING_EDEVICE.
+ * HAMMING_EDEVICE.  When a batch cannot be launched, its requests are
+ * completed with that error status (and released under auto_release), so the
+ * server keeps serving the requests behind them.
  */
 int hamming_server_progress(hamming_server *server);
 
@@ -498,8 +542,12 @@ int hamming_server_stats(hamming_server *server, uint64_t *queued, uint64_t *inf
  * Open-loop load generator: submit n requests at times start + arrival_ns[i]
  * (start = now), driving progress between arrivals, until all complete or
  * timeout_ns passes.  latency_ns[i] receives completion - scheduled arrival,
- * *elapsed_ns the wall time of the run.  Needs auto_release = 1.  Returns
- * HAMMING_OK, HAMMING_EINVAL, HAMMING_ERANGE (timeout) or a submit error.
+ * *elapsed_ns the wall time of the run.  With auto_release = 1 the trace's
+ * completions are consumed here; with auto_release = 0 they are left for
+ * hamming_server_poll (after any recorded before the call) and the outputs
+ * stay allocated until released, so the output pool must hold the outputs of
+ * the whole trace.  Returns HAMMING_OK, HAMMING_EINVAL, HAMMING_ERANGE
+ * (timeout), a submit error or a progress error.
  */
 int hamming_server_run_trace(hamming_server *server, uint32_t n, const uint64_t *arrival_ns,
                              const uint64_t *in_word_off, const uint64_t *n_cw, const uint32_t *r,

@@ -49,6 +49,10 @@ _SIGNATURES = {
     "hamming_strerror": ([_i32], ctypes.c_char_p),
     "hamming_batch_layout": ([_vp, ctypes.c_uint32, ctypes.POINTER(_u64), ctypes.POINTER(_u64)], _i32),
     "hamming_batch_workspace_bytes": ([ctypes.c_uint32], _u64),
+    "hamming_batch_workspace_min_bytes": ([ctypes.c_uint32], _u64),
+    "hamming_decode_grid": ([_u64, _i32], _u64),
+    "hamming_decode_batch_grid": ([_u64, ctypes.c_uint32, _u64], _u64),
+    "hamming_batch_release_graphs": ([], _i32),
     "hamming_decode_batch": ([_vp, _u64, _vp, _vp, ctypes.c_uint32, _u64, _vp, _u64, _vp, _u64, _vp, _vp, _u64,
                               _vp], _i32),
     "hamming_batch_config_set": ([_i32, ctypes.c_uint32, ctypes.c_uint32, _i32], _i32),
@@ -225,6 +229,22 @@ def hamming_batch_layout(descs) -> tuple[int, int]:
 
 def hamming_batch_workspace_bytes(max_packets: int) -> int:
     return int(library().hamming_batch_workspace_bytes(max_packets))
+
+
+def hamming_batch_workspace_min_bytes(max_packets: int) -> int:
+    return int(library().hamming_batch_workspace_min_bytes(max_packets))
+
+
+def hamming_decode_grid(n_cw: int, r: int) -> int:
+    return int(library().hamming_decode_grid(n_cw, r))
+
+
+def hamming_decode_batch_grid(cw_words: int, max_packets: int, max_codewords: int = 0) -> int:
+    return int(library().hamming_decode_batch_grid(cw_words, max_packets, max_codewords))
+
+
+def hamming_batch_release_graphs() -> None:
+    _check(library().hamming_batch_release_graphs(), "hamming_batch_release_graphs")
 
 
 def hamming_decode_batch(cw_arena, cw_words: int, descs, n_packets_dev, max_packets: int, max_codewords: int,
@@ -458,13 +478,13 @@ class BatchDecoder:
     output arenas; ``decode`` enqueues one ``hamming_decode_batch``.
     """
 
-    def __init__(self, cw_arena, max_packets: int, device=None):
+    def __init__(self, cw_arena, max_packets: int, device=None, workspace_bytes: int | None = None):
         import torch
 
         self.device = device or cw_arena.device
         self.cw_arena = cw_arena
         self.max_packets = max_packets
-        self.ws_bytes = hamming_batch_workspace_bytes(max_packets)
+        self.ws_bytes = workspace_bytes or hamming_batch_workspace_bytes(max_packets)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.descs_dev = torch.zeros(max_packets * 40, dtype=torch.uint8, device=self.device)
         self.n_dev = torch.zeros(1, dtype=torch.int32, device=self.device)
@@ -491,6 +511,15 @@ class BatchDecoder:
             self.errpos = torch.empty(max(1, errpos_bytes), dtype=torch.uint8, device=self.device)
         self.data_words = data_words
         self.errpos_bytes = errpos_bytes
+
+    def totals(self) -> dict:
+        """Batch totals the last decode left in the workspace header."""
+        import numpy as np
+
+        h = self.workspace[:32].cpu().numpy()
+        q = h[:16].view(np.uint64)
+        g = h[16:24].view(np.uint32)
+        return {"tiles": int(q[0]), "packets": int(q[1]), "coarse_log2": int(g[0]), "fine_log2": int(g[1])}
 
     def decode(self, stream=None, max_codewords: int = 0):
         hamming_decode_batch(self.cw_arena, self.cw_arena.numel(), self.descs_dev, self.n_dev, self.max_packets,

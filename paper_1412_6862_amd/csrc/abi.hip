@@ -98,6 +98,14 @@ int hamming_plain_config_get(int r, int* lane_codewords, uint64_t* max_blocks, u
     return HAMMING_OK;
 }
 
+uint64_t hamming_decode_grid(uint64_t n_cw, int r)
+{
+    if (!valid_r(r) || n_cw > HAMMING_MAX_CODEWORDS) return 0;
+    const uint64_t cw_per_tile = 64ull * uint64_t(g_plain[r - 3].u.load(std::memory_order_relaxed));
+    return hm::plain_grid_blocks((n_cw + cw_per_tile - 1) / cw_per_tile,
+                                 g_plain[r - 3].max_blocks.load(std::memory_order_relaxed));
+}
+
 const char* hamming_strerror(int status)
 {
     switch (status) {

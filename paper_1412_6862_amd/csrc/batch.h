@@ -45,17 +45,39 @@ struct BatchArgs {
 };
 
 inline uint32_t batch_coarse_capacity(uint32_t max_packets) { return 2 * max_packets + 1024; }
-inline uint32_t batch_fine_capacity(uint32_t max_packets)
+
+// Fine-map entries of the recommended workspace: one per tile of batches up
+// to 2^24 tiles (or 4 per packet), so the map is exact for every usual batch.
+inline uint32_t batch_fine_capacity_full(uint32_t max_packets)
 {
     return (4 * max_packets > (1u << 24)) ? 4 * max_packets : (1u << 24);
 }
 
+// Workspace bytes before the fine map: header, tile prefix sums, coarse map.
+inline uint64_t batch_workspace_fixed_bytes(uint32_t max_packets)
+{
+    return sizeof(BatchWs) + 8ull * (uint64_t(max_packets) + 1) + 4ull * batch_coarse_capacity(max_packets);
+}
 
+// Smallest workspace a call accepts: the fixed part plus one fine entry.
+inline uint64_t batch_workspace_min_bytes(uint32_t max_packets) { return batch_workspace_fixed_bytes(max_packets) + 4; }
+
+// Recommended workspace (hamming_batch_workspace_bytes).
 inline uint64_t batch_workspace_bytes(uint32_t max_packets)
 {
-    const uint64_t b = sizeof(BatchWs) + 8ull * (uint64_t(max_packets) + 1) +
-                       4ull * batch_coarse_capacity(max_packets) + 4ull * batch_fine_capacity(max_packets);
+    const uint64_t b = batch_workspace_fixed_bytes(max_packets) + 4ull * batch_fine_capacity_full(max_packets);
     return (b + 255) & ~uint64_t(255);
+}
+
+// Fine-map entries that a workspace of `bytes` (at least the minimum) holds,
+// capped at the recommended count.  A map with fewer entries than tiles
+// groups 2^g tiles per entry; the decode kernel then finds a tile's packet by
+// a 64-lane probe of the prefix sums from the entry's packet on.
+inline uint32_t batch_fine_capacity(uint32_t max_packets, uint64_t bytes)
+{
+    const uint64_t room = (bytes - batch_workspace_fixed_bytes(max_packets)) / 4;
+    const uint64_t full = batch_fine_capacity_full(max_packets);
+    return uint32_t(room < full ? room : full);
 }
 
 // Smallest codeword count of one tile over every r and schedule; sizes the
@@ -67,6 +89,17 @@ constexpr uint64_t kMinTileWords = 256;
 constexpr uint64_t kWavesPerBlockHost = 4;
 
 hipError_t launch_batch(const BatchArgs& a, int schedule, uint32_t grid, hipStream_t stream);
+
+// Validate the arguments of hamming_decode_batch, lay the caller's workspace
+// out and size the decode grid.  Returns a status code; *out and *grid are
+// set on HAMMING_OK.
+int batch_prepare(const uint64_t* cw_arena, uint64_t cw_words, const hamming_packet* descs,
+                  const uint32_t* n_packets_dev, uint32_t max_packets, uint64_t max_codewords, uint64_t* data_arena,
+                  uint64_t data_words, uint8_t* errpos_arena, uint64_t errpos_bytes, int32_t* status_out,
+                  void* workspace, uint64_t workspace_bytes, BatchArgs* out, uint32_t* grid);
+
+// The batch schedule in force (hamming_batch_config_set).
+int batch_schedule();
 
 // A batch small enough to travel in the kernel arguments: its descriptors
 // and the exclusive prefix sum of their tile counts, computed on the host by
@@ -82,6 +115,40 @@ struct SmallBatch {
     uint64_t tile_start[kSmallBatchMax + 1];
     hamming_packet descs[kSmallBatchMax];
 };
+
+// A batch planned on the host by a caller that has validated its
+// descriptors itself (the server): the exclusive prefix sum of the packets'
+// tile counts, a coarse tile-to-packet map (entry j = the packet holding tile
+// j << coarse_log2) and the descriptors, uploaded in one copy.  One launch of
+// decode_planned_batch_kernel then replaces the plan and map kernels: a wave
+// reads its map entry and probes the prefix sums 64 entries at a time from
+// there.  The map has at most about two entries per packet, so the probe
+// almost always ends in its first step.
+struct PlannedBatch {
+    const uint64_t* cw_arena;
+    uint64_t* data_arena;
+    uint8_t* errpos_arena;
+    const uint64_t* tile_start;     // device, n + 1 entries
+    const uint32_t* coarse;         // device, ceil(total_tiles / 2^coarse_log2) entries
+    const hamming_packet* descs;    // device, n entries
+    uint64_t total_tiles;           // tile_start[n], at least 1
+    uint32_t n;
+    uint32_t coarse_log2;
+    uint32_t xcd_chunk;
+    uint32_t reserved;
+};
+
+// Coarse-map entries a host plan of n packets may use.
+inline uint64_t planned_coarse_capacity(uint32_t n) { return 2ull * n + 64; }
+
+// Bytes of a host plan of n packets: prefix sums, coarse map (padded to 8
+// bytes), descriptors.
+inline uint64_t planned_bytes(uint32_t n)
+{
+    return 8ull * (n + 1) + ((4ull * planned_coarse_capacity(n) + 7) & ~7ull) + sizeof(hamming_packet) * n;
+}
+
+hipError_t launch_planned_batch(const PlannedBatch& b, int schedule, hipStream_t stream);
 
 // Codewords per lane of a tile of r-bit codewords in a batch schedule (a
 // tile is 64 lanes); 0 for an unknown schedule or r.

@@ -10,6 +10,7 @@
 
 #include "batch.h"
 #include "hamming.h"
+#include "launch.h"
 
 namespace {
 
@@ -19,9 +20,6 @@ std::atomic<int> g_schedule{3};
 std::atomic<uint32_t> g_grid_cap{0};
 std::atomic<uint32_t> g_xcd_chunk{1};
 std::atomic<int> g_use_graph{1};
-
-// Upper bound on grid size (blocks of four waves).
-constexpr uint64_t kMaxGridBlocks = (uint64_t(1) << 31) - 1;
 
 struct GraphKey {
     BatchArgs a;
@@ -37,8 +35,10 @@ struct GraphEntry {
     hipGraphExec_t exec;
 };
 
-// Executable graphs are kept until the process ends; once the cache is full,
-// calls with new argument sets launch directly.
+// Executable graphs are kept until hamming_batch_release_graphs (or the end of
+// the process); once the cache is full, calls with new argument sets launch
+// directly.  They are not destroyed from a static destructor: at process exit
+// that would call into the HIP runtime after its own teardown may have run.
 constexpr size_t kMaxGraphs = 64;
 std::mutex g_graph_mu;
 std::vector<GraphEntry> g_graphs;
@@ -78,7 +78,80 @@ hipGraphExec_t find_or_capture(const GraphKey& key, hipStream_t stream)
 
 bool misaligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) != 0; }
 
+// Upper bound on the tiles of any batch the arguments allow: the input arena
+// bounds the codewords as well as the caller's hint does, so the tighter of
+// the two is taken, plus one partial tile per packet.
+uint64_t batch_tile_bound(uint64_t cw_words, uint32_t max_packets, uint64_t max_codewords)
+{
+    uint64_t tiles = cw_words / hm::kMinTileWords;
+    if (max_codewords && max_codewords / hm::kMinTileCodewords < tiles) tiles = max_codewords / hm::kMinTileCodewords;
+    return tiles + uint64_t(max_packets);
+}
+
+// Workgroups of the batched decode kernel: one wave per tile of the bound
+// (waves beyond the real tile count only read the totals and exit, but at 4x
+// the tile count they cost a visible tail), capped by the configured cap and
+// by the dispatch limit, beyond which waves loop over tiles.
+uint64_t batch_grid_blocks(uint64_t cw_words, uint32_t max_packets, uint64_t max_codewords, uint64_t cap)
+{
+    uint64_t blocks = (batch_tile_bound(cw_words, max_packets, max_codewords) + hm::kWavesPerBlockHost - 1) /
+                      hm::kWavesPerBlockHost;
+    if (cap && blocks > cap) blocks = cap;
+    if (blocks > hm::max_launch_blocks(256)) blocks = hm::max_launch_blocks(256);
+    if (blocks < 1) blocks = 1;
+    return blocks;
+}
+
 }  // namespace
+
+namespace hm {
+
+// Validate the arguments of a batched decode and lay the workspace out.
+int batch_prepare(const uint64_t* cw_arena, uint64_t cw_words, const hamming_packet* descs,
+                  const uint32_t* n_packets_dev, uint32_t max_packets, uint64_t max_codewords, uint64_t* data_arena,
+                  uint64_t data_words, uint8_t* errpos_arena, uint64_t errpos_bytes, int32_t* status_out,
+                  void* workspace, uint64_t workspace_bytes, BatchArgs* out, uint32_t* grid)
+{
+    if (max_packets > HAMMING_MAX_BATCH) return HAMMING_ERANGE;
+    if (!cw_arena || !descs || !n_packets_dev || !data_arena || !workspace) return HAMMING_EINVAL;
+    if (misaligned(cw_arena, 8) || misaligned(data_arena, 8) || misaligned(descs, 8) ||
+        misaligned(n_packets_dev, 4) || misaligned(workspace, 8) || (status_out && misaligned(status_out, 4)))
+        return HAMMING_EALIGN;
+    if (workspace_bytes < hm::batch_workspace_min_bytes(max_packets)) return HAMMING_ENOMEM;
+
+    BatchArgs& a = *out;
+    memset(&a, 0, sizeof a);
+    a.cw_arena = cw_arena;
+    a.cw_words = cw_words;
+    a.descs = descs;
+    a.n_packets_dev = n_packets_dev;
+    a.max_packets = max_packets;
+    a.data_arena = data_arena;
+    a.data_words = data_words;
+    a.errpos_arena = errpos_arena;
+    a.errpos_bytes = errpos_arena ? errpos_bytes : 0;
+    a.status_out = status_out;
+    a.xcd_chunk = g_xcd_chunk.load();
+    a.coarse_cap = hm::batch_coarse_capacity(max_packets);
+    a.fine_cap = hm::batch_fine_capacity(max_packets, workspace_bytes);
+    a.ws = static_cast<hm::BatchWs*>(workspace);
+    a.tile_start = reinterpret_cast<uint64_t*>(static_cast<char*>(workspace) + sizeof(hm::BatchWs));
+    a.coarse = reinterpret_cast<uint32_t*>(a.tile_start + (uint64_t(max_packets) + 1));
+    a.fine = a.coarse + a.coarse_cap;
+
+    const uint64_t blocks = batch_grid_blocks(cw_words, max_packets, max_codewords, g_grid_cap.load());
+    *grid = uint32_t(blocks);
+    // the fine map has at most one entry per tile of the bound (its kernel is
+    // grid-stride, so this only sizes its grid)
+    const uint64_t tiles = batch_tile_bound(cw_words, max_packets, max_codewords);
+    const uint64_t fine_entries = tiles < a.fine_cap ? tiles : a.fine_cap;
+    a.fine_blocks = uint32_t((fine_entries + 255) / 256);
+    return HAMMING_OK;
+}
+
+int batch_schedule() { return g_schedule.load(); }
+
+}  // namespace hm
 
 extern "C" {
 
@@ -86,6 +159,12 @@ uint64_t hamming_batch_workspace_bytes(uint32_t max_packets)
 {
     if (max_packets > HAMMING_MAX_BATCH) return 0;
     return hm::batch_workspace_bytes(max_packets);
+}
+
+uint64_t hamming_batch_workspace_min_bytes(uint32_t max_packets)
+{
+    if (max_packets > HAMMING_MAX_BATCH) return 0;
+    return hm::batch_workspace_min_bytes(max_packets);
 }
 
 int hamming_batch_layout(hamming_packet* descs, uint32_t n, uint64_t* data_words, uint64_t* errpos_bytes)
@@ -134,59 +213,19 @@ int hamming_batch_config_get(int* schedule, uint32_t* xcd_chunk, uint32_t* grid_
 
 int hamming_decode_batch(const uint64_t* cw_arena, uint64_t cw_words, const hamming_packet* descs,
                          const uint32_t* n_packets_dev, uint32_t max_packets, uint64_t max_codewords,
-                         uint64_t* data_arena,
-                         uint64_t data_words, uint8_t* errpos_arena, uint64_t errpos_bytes,
+                         uint64_t* data_arena, uint64_t data_words, uint8_t* errpos_arena, uint64_t errpos_bytes,
                          int32_t* status_out, void* workspace, uint64_t workspace_bytes, hipStream_t stream)
 {
     if (max_packets > HAMMING_MAX_BATCH) return HAMMING_ERANGE;
     if (max_packets == 0) return HAMMING_OK;
-    if (!cw_arena || !descs || !n_packets_dev || !data_arena || !workspace) return HAMMING_EINVAL;
-    if (misaligned(cw_arena, 8) || misaligned(data_arena, 8) || misaligned(descs, 8) ||
-        misaligned(n_packets_dev, 4) || misaligned(workspace, 8) || (status_out && misaligned(status_out, 4)))
-        return HAMMING_EALIGN;
-    if (workspace_bytes < hm::batch_workspace_bytes(max_packets)) return HAMMING_ENOMEM;
-
     BatchArgs a;
-    memset(&a, 0, sizeof a);
-    a.cw_arena = cw_arena;
-    a.cw_words = cw_words;
-    a.descs = descs;
-    a.n_packets_dev = n_packets_dev;
-    a.max_packets = max_packets;
-    a.data_arena = data_arena;
-    a.data_words = data_words;
-    a.errpos_arena = errpos_arena;
-    a.errpos_bytes = errpos_arena ? errpos_bytes : 0;
-    a.status_out = status_out;
-    a.xcd_chunk = g_xcd_chunk.load();
-    a.coarse_cap = hm::batch_coarse_capacity(max_packets);
-    a.fine_cap = hm::batch_fine_capacity(max_packets);
-    a.ws = static_cast<hm::BatchWs*>(workspace);
-    a.tile_start = reinterpret_cast<uint64_t*>(static_cast<char*>(workspace) + sizeof(hm::BatchWs));
-    a.coarse = reinterpret_cast<uint32_t*>(a.tile_start + (uint64_t(max_packets) + 1));
-    a.fine = a.coarse + a.coarse_cap;
-
+    uint32_t grid = 0;
+    const int rc = hm::batch_prepare(cw_arena, cw_words, descs, n_packets_dev, max_packets, max_codewords, data_arena,
+                           data_words, errpos_arena, errpos_bytes, status_out, workspace, workspace_bytes, &a, &grid);
+    if (rc != HAMMING_OK) return rc;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return HAMMING_EDEVICE;
     const int schedule = g_schedule.load();
-    // One wave per tile of the largest batch these arguments allow; a smaller
-    // grid is still correct (waves loop), only slower.
-    // the input arena bounds the codewords as well as the hint does; take the
-    // tighter of the two (excess waves only read the totals and exit, but at
-    // 4x the real tile count they cost a noticeable tail)
-    uint64_t tiles = cw_words / hm::kMinTileWords;
-    if (max_codewords && max_codewords / hm::kMinTileCodewords < tiles) tiles = max_codewords / hm::kMinTileCodewords;
-    tiles += uint64_t(max_packets);
-    uint64_t blocks = (tiles + hm::kWavesPerBlockHost - 1) / hm::kWavesPerBlockHost;
-    const uint64_t cap = g_grid_cap.load();
-    if (cap && blocks > cap) blocks = cap;
-    if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
-    if (blocks < 1) blocks = 1;
-    const uint32_t grid = uint32_t(blocks);
-    // the fine map has at most one entry per tile of that bound
-    const uint64_t fine_entries = tiles < a.fine_cap ? tiles : a.fine_cap;
-    a.fine_blocks = uint32_t((fine_entries + 255) / 256);
-
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (stream && hipStreamIsCapturing(stream, &cs) != hipSuccess) return HAMMING_EDEVICE;
     if (stream && cs == hipStreamCaptureStatusNone && g_use_graph.load()) {
@@ -201,6 +240,30 @@ int hamming_decode_batch(const uint64_t* cw_arena, uint64_t cw_words, const hamm
         if (exec) return hipGraphLaunch(exec, stream) == hipSuccess ? HAMMING_OK : HAMMING_EDEVICE;
     }
     return hm::launch_batch(a, schedule, grid, stream) == hipSuccess ? HAMMING_OK : HAMMING_EDEVICE;
+}
+
+int hamming_batch_release_graphs(void)
+{
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return HAMMING_EDEVICE;
+    int rc = HAMMING_OK;
+    for (auto& e : g_graphs) {
+        // a replay may still be in flight on its device
+        if (hipSetDevice(e.key.device) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+            hipGraphExecDestroy(e.exec) != hipSuccess)
+            rc = HAMMING_EDEVICE;
+    }
+    g_graphs.clear();
+    if (hipSetDevice(cur) != hipSuccess) rc = HAMMING_EDEVICE;
+    (void)hipGetLastError();
+    return rc;
+}
+
+uint64_t hamming_decode_batch_grid(uint64_t cw_words, uint32_t max_packets, uint64_t max_codewords)
+{
+    if (max_packets == 0 || max_packets > HAMMING_MAX_BATCH) return 0;
+    return batch_grid_blocks(cw_words, max_packets, max_codewords, g_grid_cap.load());
 }
 
 }  // extern "C"

@@ -25,6 +25,7 @@
 #include "batch.h"
 #include "hamming.h"
 #include "hamming_device.h"
+#include "launch.h"
 #include "tile.h"
 
 namespace hm {
@@ -261,6 +262,47 @@ void decode_small_batch_kernel(SmallBatch b)
     decode_any_tile<S>(d, t - b.tile_start[p], b.cw_arena, b.data_arena, b.errpos_arena, lds);
 }
 
+// The host-planned form: one tile per wave in global tile order (waves loop
+// when the batch has more tiles than a dispatch can hold), the packet found
+// from the coarse map entry by a 64-lane probe of the prefix sums.
+template <class S>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(S::waves_per_simd)))
+void decode_planned_batch_kernel(PlannedBatch b)
+{
+    __shared__ u32x4 lds_raw[kWavesPerBlock][S::LDS_MAX / 4];
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t* lds = reinterpret_cast<uint32_t*>(&lds_raw[wave][0]);
+    const uint64_t waves = uint64_t(gridDim.x) * kWavesPerBlock;
+    for (uint64_t t = uint64_t(xcd_block(blockIdx.x, gridDim.x, b.xcd_chunk)) * kWavesPerBlock + wave;
+         t < b.total_tiles; t += waves) {
+        const uint32_t p = probe_packet(b.tile_start, b.n, t, b.coarse[t >> b.coarse_log2]);
+        const hamming_packet d = b.descs[p];
+        decode_any_tile<S>(d, t - b.tile_start[p], b.cw_arena, b.data_arena, b.errpos_arena, lds);
+    }
+}
+
+template <class S>
+static hipError_t launch_planned_s(const PlannedBatch& b, hipStream_t stream)
+{
+    uint64_t blocks = (b.total_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks > max_launch_blocks(kBlockThreads)) blocks = max_launch_blocks(kBlockThreads);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL((decode_planned_batch_kernel<S>), dim3(uint32_t(blocks)), dim3(kBlockThreads), 0, stream, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_planned_batch(const PlannedBatch& b, int schedule, hipStream_t stream)
+{
+    if (b.n < 1) return hipErrorInvalidValue;
+    switch (schedule) {
+    case 0: return launch_planned_s<Sched0>(b, stream);
+    case 1: return launch_planned_s<Sched1>(b, stream);
+    case 2: return launch_planned_s<Sched2>(b, stream);
+    case 3: return launch_planned_s<Sched3>(b, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <class S>
 static hipError_t launch_batch_s(const BatchArgs& a, uint32_t grid, hipStream_t stream)
 {
@@ -282,7 +324,7 @@ template <class S>
 static hipError_t launch_small_s(const SmallBatch& b, hipStream_t stream)
 {
     const uint64_t blocks = (b.tile_start[b.n] + kWavesPerBlock - 1) / kWavesPerBlock;
-    if (blocks == 0 || blocks > 0xFFFFFFFFull) return hipErrorInvalidValue;
+    if (blocks == 0 || blocks > max_launch_blocks(kBlockThreads)) return hipErrorInvalidValue;
     hipLaunchKernelGGL((decode_small_batch_kernel<S>), dim3(uint32_t(blocks)), dim3(kBlockThreads), 0, stream, b);
     return hipGetLastError();
 }

@@ -31,10 +31,9 @@ template <int R, int U>
 static hipError_t launch_decode_ru(const DecodeLaunch& L, hipStream_t stream)
 {
     using T = TileShape<R, U>;
+    static_assert(kWavesPerBlock == 4 && kBlockThreads == 256, "plain_grid_blocks assumes 4-wave workgroups");
     const uint64_t n_tiles = (L.n_cw + T::CW - 1) / T::CW;
-    uint64_t blocks = (n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    const uint64_t cap = L.max_blocks ? L.max_blocks : blocks;
-    if (blocks > cap) blocks = cap;
+    const uint64_t blocks = plain_grid_blocks(n_tiles, L.max_blocks);
     if (blocks == 0) return hipSuccess;
     uint32_t flags = 0;
     if ((reinterpret_cast<uintptr_t>(L.cw) & 15u) == 0) flags |= kFlagIn16;

@@ -23,6 +23,22 @@ struct DecodeLaunch {
     uint32_t xcd_chunk;     // blocks per XCD slice (1 = hardware order)
 };
 
+// A dispatch packet holds its grid size in work-items as a 32-bit field, so
+// one launch has at most this many workgroups of `threads` work-items.
+constexpr uint64_t kMaxDispatchItems = 0xFFFFFFFFull;
+constexpr uint64_t max_launch_blocks(uint64_t threads) { return kMaxDispatchItems / threads; }
+
+// Workgroups (of 4 waves) of a plain decode launch over n_tiles wave tiles:
+// one wave per tile, capped by max_blocks (0 = no cap) and by the dispatch
+// limit; the kernel's waves loop over the tiles beyond the grid.
+constexpr uint64_t plain_grid_blocks(uint64_t n_tiles, uint64_t max_blocks)
+{
+    uint64_t blocks = (n_tiles + 3) / 4;
+    if (max_blocks && blocks > max_blocks) blocks = max_blocks;
+    if (blocks > max_launch_blocks(256)) blocks = max_launch_blocks(256);
+    return blocks;
+}
+
 // Smallest lane width that gives every lane chunk at least one dword.
 constexpr bool valid_u(int r, int u)
 {

@@ -283,6 +283,10 @@ void launch_to_planes(const uint64_t* cw, uint64_t n_cw, uint64_t* planes, uint6
 
 extern "C" {
 
+// One launch covers at most this many codewords: both plane kernels then
+// stay within a dispatch's 32-bit work-item count (one lane per 32 codewords).
+constexpr uint64_t kPlanesMaxCodewords = (uint64_t(1) << 37) - (uint64_t(1) << 13);
+
 uint64_t hamming_planes_words(uint64_t n_cw, int r)
 {
     if (r < 3 || r > 7 || n_cw > HAMMING_MAX_CODEWORDS) return 0;
@@ -293,7 +297,7 @@ int hamming_decode_planes(const uint64_t* planes, uint64_t plane_words, uint64_t
                           uint8_t* errpos_out, hipStream_t stream)
 {
     if (r < 3 || r > 7) return HAMMING_EINVAL;
-    if (n_cw > HAMMING_MAX_CODEWORDS) return HAMMING_ERANGE;
+    if (n_cw > kPlanesMaxCodewords) return HAMMING_ERANGE;
     if (n_cw == 0) return HAMMING_OK;
     if (!planes || !data_out) return HAMMING_EINVAL;
     if (plane_words < (n_cw + 63) / 64) return HAMMING_ERANGE;
@@ -316,7 +320,7 @@ int hamming_to_planes(const uint64_t* codewords, uint64_t n_cw, int r, uint64_t*
                       hipStream_t stream)
 {
     if (r < 3 || r > 7) return HAMMING_EINVAL;
-    if (n_cw > HAMMING_MAX_CODEWORDS) return HAMMING_ERANGE;
+    if (n_cw > kPlanesMaxCodewords) return HAMMING_ERANGE;
     if (n_cw == 0) return HAMMING_OK;
     if (!codewords || !planes) return HAMMING_EINVAL;
     if (plane_words < (n_cw + 63) / 64) return HAMMING_ERANGE;

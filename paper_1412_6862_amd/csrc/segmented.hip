@@ -23,6 +23,7 @@
 #include <atomic>
 
 #include "hamming.h"
+#include "launch.h"
 #include "tile.h"
 
 using hm::wave_sync;
@@ -557,8 +558,18 @@ void launch(const SegArgs& a, uint32_t n_packets, uint32_t max_msg_bytes, hipStr
         kernel = seg_kernel<256, 2, DECODE>();
     const uint32_t per_block = 64 * kSegWaves / group;
     const size_t lds = size_t(per_block) * (a.slice_words + kAccWords) * 8;
-    const uint32_t blocks = (n_packets + per_block - 1) / per_block;
-    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(64 * kSegWaves), lds, stream, a);
+    // one launch per slice of packets that fits a dispatch's 32-bit work-item
+    // count; a slice addresses its packets through offset descriptor and
+    // status pointers (syndromes are placed by each descriptor's seg_off)
+    const uint64_t per_launch = hm::max_launch_blocks(64 * kSegWaves) * per_block;
+    for (uint64_t first = 0; first < n_packets; first += per_launch) {
+        SegArgs s = a;
+        s.descs = a.descs + first;
+        s.status = a.status ? a.status + first : nullptr;
+        s.n_packets = uint32_t(n_packets - first < per_launch ? n_packets - first : per_launch);
+        const uint32_t blocks = (s.n_packets + per_block - 1) / per_block;
+        hipLaunchKernelGGL(kernel, dim3(blocks), dim3(64 * kSegWaves), lds, stream, s);
+    }
 }
 
 int check_common(const void* enc, const void* descs, uint32_t n_packets, const void* msg, uint32_t max_msg_bytes)

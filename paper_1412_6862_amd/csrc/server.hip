@@ -5,9 +5,12 @@
 // carved from the output pool) -> placed in the next batch of a free slot ->
 // the slot launches the batch on its own stream: a batch of at most 16
 // requests and 2^20 codewords is one decode launch with its descriptors in
-// the kernel arguments, a larger one copies its descriptors to the device and
-// replays its batch graph -> progress() sees the slot's event complete -> a
-// completion record is queued (and the outputs freed when auto_release).
+// the kernel arguments; a larger one is planned on the host (tile prefix sums
+// and a coarse tile-to-packet map next to the descriptors), copied to the
+// device in one transfer and decoded by one launch -> progress() sees the
+// slot's event complete -> a completion record is queued (and the outputs
+// freed when auto_release).  The server validated every request at
+// submission, so no planning or validation runs on the device.
 // New batches launch whenever a slot is free, so arrivals overlap with
 // batches already on the GPU.
 //
@@ -111,18 +114,11 @@ private:
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    unsigned char* host = nullptr;     // pinned: n_packets (uint32, padded to 8) + descriptors
-    uint32_t* n_dev = nullptr;         // device: n_packets then the descriptors
-    hamming_packet* descs_dev = nullptr;
-    void* ws = nullptr;
-    uint64_t ws_bytes = 0;
-    uint64_t first = 0, count = 0;     // request ids [first, first + count)
+    unsigned char* plan_host = nullptr;   // pinned: the host plan of the slot's batch
+    unsigned char* plan_dev = nullptr;    // device: its copy, read by the decode kernel
+    uint64_t first = 0, count = 0;        // request ids [first, first + count)
     bool busy = false;
 };
-
-// Grid-size hints (codewords) below the largest batch: one graph per tier per
-// slot, so a small batch does not launch the grid of the largest one.
-constexpr uint64_t kTiers[] = {uint64_t(1) << 18, uint64_t(1) << 21, uint64_t(1) << 24};
 
 }  // namespace
 
@@ -157,9 +153,8 @@ void free_server(hamming_server* s)
     for (auto& sl : s->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.done) (void)hipEventDestroy(sl.done);
-        if (sl.host) (void)hipHostFree(sl.host);
-        if (sl.n_dev) (void)hipFree(sl.n_dev);          // also holds descs_dev
-        if (sl.ws) (void)hipFree(sl.ws);
+        if (sl.plan_host) (void)hipHostFree(sl.plan_host);
+        if (sl.plan_dev) (void)hipFree(sl.plan_dev);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
     delete s;
@@ -205,35 +200,104 @@ int reap(hamming_server* s)
     return HAMMING_OK;
 }
 
+// Tile prefix sums of a batch's descriptors under the batch schedule in
+// force (tiles of 64 lanes of schedule_lane_width codewords each).
+bool tile_prefix(const hamming_packet* descs, uint32_t n, int schedule, uint64_t* ts)
+{
+    ts[0] = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t cwt = 64ull * hm::schedule_lane_width(schedule, descs[i].r);
+        if (cwt == 0) return false;
+        ts[i + 1] = ts[i] + (descs[i].n_cw + cwt - 1) / cwt;
+    }
+    return true;
+}
+
 // A batch of at most hm::kSmallBatchMax requests: the descriptors (checked
 // at submission, outputs carved from the pool) and their tile prefix sums go
 // to the decode kernel in its arguments, in one launch.
-int launch_small(hamming_server* s, const hamming_packet* descs, uint32_t n, hipStream_t stream)
+int launch_small(hamming_server* s, const hamming_packet* descs, uint32_t n, int schedule, hipStream_t stream)
 {
-    int schedule = 0, use_graph = 0;
-    uint32_t xcd_chunk = 0, grid_cap = 0;
-    if (hamming_batch_config_get(&schedule, &xcd_chunk, &grid_cap, &use_graph) != HAMMING_OK) return HAMMING_EDEVICE;
     hm::SmallBatch b{};
     b.cw_arena = s->pool;
     b.data_arena = reinterpret_cast<uint64_t*>(s->out_base);
     b.errpos_arena = s->out_base;
     b.n = n;
-    b.tile_start[0] = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-        b.descs[i] = descs[i];
-        const uint64_t cwt = 64ull * hm::schedule_lane_width(schedule, descs[i].r);
-        if (cwt == 0) return HAMMING_EINVAL;
-        b.tile_start[i + 1] = b.tile_start[i] + (descs[i].n_cw + cwt - 1) / cwt;
-    }
+    for (uint32_t i = 0; i < n; ++i) b.descs[i] = descs[i];
+    if (!tile_prefix(descs, n, schedule, b.tile_start)) return HAMMING_EINVAL;
     if (b.tile_start[n] == 0) return HAMMING_OK;                 // nothing but empty requests
     return hm::launch_small_batch(b, schedule, stream) == hipSuccess ? HAMMING_OK : HAMMING_EDEVICE;
 }
 
+// A larger batch: the host plan (descriptors, already in the slot's pinned
+// buffer, then the tile prefix sums and a coarse tile-to-packet map) goes to
+// the device in one copy, followed by one decode launch.
+int launch_planned(hamming_server* s, Slot& sl, uint32_t n, int schedule, uint32_t xcd_chunk)
+{
+    const auto* descs = reinterpret_cast<const hamming_packet*>(sl.plan_host);
+    const uint64_t ts_off = sizeof(hamming_packet) * uint64_t(n);
+    auto* ts = reinterpret_cast<uint64_t*>(sl.plan_host + ts_off);
+    if (!tile_prefix(descs, n, schedule, ts)) return HAMMING_EINVAL;
+    const uint64_t total = ts[n];
+    if (total == 0) return HAMMING_OK;
+    // entry j = the packet holding tile j << g, at most planned_coarse_capacity(n) entries
+    const uint64_t cap = hm::planned_coarse_capacity(n);
+    uint32_t g = 0;
+    while ((total >> g) >= cap) ++g;
+    const uint64_t entries = (total + (uint64_t(1) << g) - 1) >> g;
+    const uint64_t coarse_off = ts_off + 8ull * (n + 1);
+    auto* coarse = reinterpret_cast<uint32_t*>(sl.plan_host + coarse_off);
+    uint64_t j = 0;
+    for (uint32_t p = 0; p < n && j < entries; ++p)
+        while (j < entries && (j << g) < ts[p + 1]) coarse[j++] = p;
+    const uint64_t bytes = coarse_off + 4 * entries;
+    if (hipMemcpyAsync(sl.plan_dev, sl.plan_host, bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
+        return HAMMING_EDEVICE;
+    hm::PlannedBatch b{};
+    b.cw_arena = s->pool;
+    b.data_arena = reinterpret_cast<uint64_t*>(s->out_base);
+    b.errpos_arena = s->out_base;
+    b.descs = reinterpret_cast<const hamming_packet*>(sl.plan_dev);
+    b.tile_start = reinterpret_cast<const uint64_t*>(sl.plan_dev + ts_off);
+    b.coarse = reinterpret_cast<const uint32_t*>(sl.plan_dev + coarse_off);
+    b.total_tiles = total;
+    b.n = n;
+    b.coarse_log2 = g;
+    b.xcd_chunk = xcd_chunk;
+    return hm::launch_planned_batch(b, schedule, sl.stream) == hipSuccess ? HAMMING_OK : HAMMING_EDEVICE;
+}
+
+// Requests [first, first + n) were admitted but their batch could not be
+// launched: complete them with the error status (releasing their outputs when
+// auto_release is set, else leaving that to the caller) so the queue and the
+// output pool keep moving.
+void fail_batch(hamming_server* s, uint64_t first, uint32_t n, int status)
+{
+    const uint64_t t = now_ns();
+    for (uint64_t id = first; id < first + n; ++id) {
+        Request& rq = s->req(id);
+        hamming_completion c;
+        c.request_id = id;
+        c.data_offset = rq.out_off;
+        c.errpos_offset = rq.out_off + round_up(rq.data_bytes, 16);
+        c.submit_ns = rq.arrival_ns;
+        c.complete_ns = t;
+        c.status = status;
+        c.reserved = 0;
+        s->completions.push_back(c);
+        rq.state = s->cfg.auto_release ? kReleased : kDone;
+    }
+    if (s->cfg.auto_release) reclaim(s);
+}
+
 int launch(hamming_server* s)
 {
+    int schedule = 0, use_graph = 0;
+    uint32_t xcd_chunk = 0, grid_cap = 0;
+    if (hamming_batch_config_get(&schedule, &xcd_chunk, &grid_cap, &use_graph) != HAMMING_OK) return HAMMING_EDEVICE;
     for (auto& sl : s->slots) {
         if (sl.busy || s->next_admit == s->next_id) continue;
-        auto* descs = reinterpret_cast<hamming_packet*>(sl.host + 8);
+        auto* descs = reinterpret_cast<hamming_packet*>(sl.plan_host);
         uint32_t n = 0;
         uint64_t cws = 0;
         const uint64_t first = s->next_admit;
@@ -256,27 +320,17 @@ int launch(hamming_server* s)
             ++n;
         }
         if (n == 0) break;                                      // the head of the queue does not fit
-        if (n <= hm::kSmallBatchMax && cws <= kDirectMaxCodewords) {
-            const int rc = launch_small(s, descs, n, sl.stream);
-            if (rc != HAMMING_OK) return rc;
-        } else {
-            *reinterpret_cast<uint32_t*>(sl.host) = n;
-            if (hipMemcpyAsync(sl.n_dev, sl.host, 8 + uint64_t(n) * sizeof(hamming_packet), hipMemcpyHostToDevice,
-                               sl.stream) != hipSuccess)
-                return HAMMING_EDEVICE;
-            uint64_t hint = s->cfg.max_batch_codewords;
-            for (uint64_t tier : kTiers)
-                if (cws <= tier && tier < hint) {
-                    hint = tier;
-                    break;
-                }
-            const int rc = hamming_decode_batch(s->pool, s->pool_words, sl.descs_dev, sl.n_dev,
-                                                s->cfg.max_batch_packets, hint,
-                                                reinterpret_cast<uint64_t*>(s->out_base), s->alloc.size() / 8,
-                                                s->out_base, s->alloc.size(), nullptr, sl.ws, sl.ws_bytes, sl.stream);
-            if (rc != HAMMING_OK) return rc;
+        int rc;
+        if (n <= hm::kSmallBatchMax && cws <= kDirectMaxCodewords)
+            rc = launch_small(s, descs, n, schedule, sl.stream);
+        else
+            rc = launch_planned(s, sl, n, schedule, xcd_chunk);
+        if (rc == HAMMING_OK && hipEventRecord(sl.done, sl.stream) != hipSuccess) rc = HAMMING_EDEVICE;
+        if (rc != HAMMING_OK) {
+            (void)hipGetLastError();
+            fail_batch(s, first, n, rc);
+            return rc;
         }
-        if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return HAMMING_EDEVICE;
         sl.first = first;
         sl.count = n;
         sl.busy = true;
@@ -285,6 +339,10 @@ int launch(hamming_server* s)
     }
     return HAMMING_OK;
 }
+
+int run_trace_loop(hamming_server* s, uint32_t n, const uint64_t* arrival_ns, const uint64_t* in_word_off,
+                   const uint64_t* n_cw, const uint32_t* r, uint64_t timeout_ns, uint64_t* latency_ns,
+                   uint64_t* elapsed_ns, std::deque<hamming_completion>& keep);
 
 }  // namespace
 
@@ -319,20 +377,13 @@ int hamming_server_create(const hamming_server_config* config, const uint64_t* c
         return HAMMING_ENOMEM;
     }
     s->slots.resize(c.slots);
-    const uint64_t ws_bytes = hamming_batch_workspace_bytes(c.max_batch_packets);
+    const uint64_t plan_bytes = hm::planned_bytes(c.max_batch_packets);
     for (auto& sl : s->slots) {
-        char* dev = nullptr;
-        const uint64_t dbytes = 8 + uint64_t(c.max_batch_packets) * sizeof(hamming_packet);
-        bool ok = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
-                  hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
-                  hipHostMalloc(reinterpret_cast<void**>(&sl.host), dbytes, hipHostMallocDefault) == hipSuccess &&
-                  hipMalloc(reinterpret_cast<void**>(&dev), dbytes) == hipSuccess;
-        if (ok) {
-            sl.n_dev = reinterpret_cast<uint32_t*>(dev);
-            sl.descs_dev = reinterpret_cast<hamming_packet*>(dev + 8);
-            ok = hipMalloc(&sl.ws, ws_bytes) == hipSuccess;
-            sl.ws_bytes = ws_bytes;
-        }
+        const bool ok =
+            hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
+            hipHostMalloc(reinterpret_cast<void**>(&sl.plan_host), plan_bytes, hipHostMallocDefault) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void**>(&sl.plan_dev), plan_bytes) == hipSuccess;
         if (!ok) {
             (void)hipGetLastError();
             free_server(s);
@@ -429,10 +480,27 @@ int hamming_server_run_trace(hamming_server* s, uint32_t n, const uint64_t* arri
                              const uint64_t* n_cw, const uint32_t* r, uint64_t timeout_ns, uint64_t* latency_ns,
                              uint64_t* elapsed_ns)
 {
-    if (!s || !s->cfg.auto_release || (n && (!arrival_ns || !in_word_off || !n_cw || !r || !latency_ns)) ||
-        !elapsed_ns)
+    if (!s || (n && (!arrival_ns || !in_word_off || !n_cw || !r || !latency_ns)) || !elapsed_ns)
         return HAMMING_EINVAL;
-    s->completions.clear();
+    // completions recorded before the trace stay for the caller; without
+    // auto_release the trace's own are kept after them (their outputs stay
+    // allocated until released)
+    std::deque<hamming_completion> keep;
+    keep.swap(s->completions);
+    const int rc = run_trace_loop(s, n, arrival_ns, in_word_off, n_cw, r, timeout_ns, latency_ns, elapsed_ns, keep);
+    for (const auto& c : s->completions) keep.push_back(c);
+    s->completions.swap(keep);
+    return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+int run_trace_loop(hamming_server* s, uint32_t n, const uint64_t* arrival_ns, const uint64_t* in_word_off,
+                   const uint64_t* n_cw, const uint32_t* r, uint64_t timeout_ns, uint64_t* latency_ns,
+                   uint64_t* elapsed_ns, std::deque<hamming_completion>& keep)
+{
     const uint64_t first_id = s->next_id;             // trace request i gets id first_id + i
     const uint64_t start = now_ns();
     uint32_t next = 0, finished = 0;
@@ -455,6 +523,7 @@ int hamming_server_run_trace(hamming_server* s, uint32_t n, const uint64_t* arri
                 latency_ns[c.request_id - first_id] = c.complete_ns - c.submit_ns;
                 ++finished;
             }
+            if (!s->cfg.auto_release) keep.push_back(c);
             s->completions.pop_front();
         }
     }
@@ -462,4 +531,4 @@ int hamming_server_run_trace(hamming_server* s, uint32_t n, const uint64_t* arri
     return HAMMING_OK;
 }
 
-}  // extern "C"
+}  // namespace

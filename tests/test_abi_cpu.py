@@ -142,7 +142,19 @@ def test_batch_workspace_and_validation_codes():
     assert call(cw=A + 4) == hm.HAMMING_EALIGN
     assert call(descs=A + 4) == hm.HAMMING_EALIGN
     assert call(status=A + 2) == hm.HAMMING_EALIGN
-    assert call(wsb=ws - 8) == hm.HAMMING_ENOMEM
+    wmin = hm.hamming_batch_workspace_min_bytes(10)
+    assert call(wsb=wmin - 1) == hm.HAMMING_ENOMEM
+    assert call(wsb=0) == hm.HAMMING_ENOMEM
+
+
+def test_batch_workspace_sizes():
+    # header (64 bytes) + tile prefix sums (8 per packet + 1) + coarse map (4 * (2n + 1024)) before the fine map
+    for n in (0, 1, 10, 1000, 1 << 20):
+        fixed = 64 + 8 * (n + 1) + 4 * (2 * n + 1024)
+        assert hm.hamming_batch_workspace_min_bytes(n) == fixed + 4
+        full = max(4 * n, 1 << 24)
+        assert hm.hamming_batch_workspace_bytes(n) == (fixed + 4 * full + 255) // 256 * 256
+    assert hm.hamming_batch_workspace_min_bytes(hm.HAMMING_MAX_BATCH + 1) == 0
 
 
 def test_batch_config_roundtrip():
@@ -308,3 +320,52 @@ def test_segmented_mode_config_roundtrip():
                 hm.hamming_seg_config_set(bad)
     finally:
         hm.hamming_seg_config_set(old)
+
+
+DISPATCH_LIMIT_BLOCKS = (2 ** 32 - 1) // 256     # a dispatch holds at most 2^32-1 work-items
+
+
+def test_plain_grid_is_one_wave_per_tile_clamped_to_the_dispatch_limit():
+    old = {r: hm.hamming_plain_config_get(r) for r in range(3, 8)}
+    try:
+        hm.hamming_plain_config_set(6, 4, 0, 1)
+        assert hm.hamming_decode_grid(1 << 26, 6) == (1 << 26) // 256 // 4
+        assert hm.hamming_decode_grid(257, 6) == 1 and hm.hamming_decode_grid(4 * 256 + 1, 6) == 2
+        assert hm.hamming_decode_grid(0, 6) == 0 and hm.hamming_decode_grid(10, 9) == 0
+        # 2^40 codewords = 2^32 tiles = 2^30 workgroups: past the limit, so waves loop
+        assert hm.hamming_decode_grid(1 << 40, 6) == DISPATCH_LIMIT_BLOCKS
+        assert hm.hamming_decode_grid(hm.HAMMING_MAX_CODEWORDS + 1, 6) == 0
+        hm.hamming_plain_config_set(6, 4, 1000, 1)
+        assert hm.hamming_decode_grid(1 << 26, 6) == 1000
+        hm.hamming_plain_config_set(3, 16, 1 << 31, 1)          # a cap above the limit does not lift it
+        assert hm.hamming_decode_grid(1 << 40, 3) == DISPATCH_LIMIT_BLOCKS
+        assert hm.hamming_decode_grid(1 << 30, 3) == (1 << 30) // 1024 // 4
+    finally:
+        for r, (u, mb, xc) in old.items():
+            hm.hamming_plain_config_set(r, u, mb, xc)
+
+
+def test_batch_grid_bound_and_clamp():
+    old = hm.hamming_batch_config_get()
+    try:
+        hm.hamming_batch_config_set(old[0], old[1], 0, old[3])
+        # tiles <= cw_words/256 (or hint/128) + one partial tile per packet
+        assert hm.hamming_decode_batch_grid(1 << 20, 10) == (4096 + 10 + 3) // 4
+        assert hm.hamming_decode_batch_grid(1 << 20, 10, 1000) == (7 + 10 + 3) // 4
+        assert hm.hamming_decode_batch_grid(1 << 20, 10, 1 << 40) == (4096 + 10 + 3) // 4
+        assert hm.hamming_decode_batch_grid(0, 1) == 1
+        assert hm.hamming_decode_batch_grid(1 << 20, 0) == 0
+        assert hm.hamming_decode_batch_grid(1 << 20, hm.HAMMING_MAX_BATCH + 1) == 0
+        assert hm.hamming_decode_batch_grid(1 << 42, 1000) == DISPATCH_LIMIT_BLOCKS
+        hm.hamming_batch_config_set(old[0], old[1], 3, old[3])
+        assert hm.hamming_decode_batch_grid(1 << 20, 10) == 3
+    finally:
+        hm.hamming_batch_config_set(*old)
+
+
+def test_planes_reject_counts_beyond_one_launch():
+    A = 1 << 20
+    lib = hm.library()
+    big = (1 << 37) - (1 << 13) + 1
+    assert lib.hamming_decode_planes(A, big, big, 4, A, A, 0) == hm.HAMMING_ERANGE
+    assert lib.hamming_to_planes(A, big, 4, A, big, 0) == hm.HAMMING_ERANGE

@@ -238,11 +238,92 @@ def test_batch_small_grid_hint_and_coarse_map(gpu_device):
         _check_outputs(bd, descs, expect)
 
 
-def test_batch_full_size_workload_sampled_packets(gpu_device):
+def _decode_with_workspace(gpu_device, arena, descs, ws_bytes, max_codewords=0):
+    import torch
+
+    bd = hm.BatchDecoder(_to_dev(arena, gpu_device), descs.size, workspace_bytes=ws_bytes)
+    bd.set_packets(descs)
+    bd.data.fill_(0x7777777777777777)
+    bd.errpos.fill_(0x88)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        bd.decode(stream=s, max_codewords=max_codewords)
+    torch.cuda.synchronize()
+    return bd
+
+
+@pytest.mark.parametrize("fine_log2", [1, 3, 6])
+@pytest.mark.parametrize("schedule", [0, 1, 2, 3])
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_batch_grouped_fine_map_probe_path(gpu_device, fine_log2, schedule, use_graph):
+    """A workspace below the recommended size gives a fine map of 2^g tiles
+    per entry; every wave then probes the prefix sums from its entry's packet.
+    The map size is chosen from the batch's tile count so that g is exactly
+    1, 3 or 6, and the outputs must stay byte-exact."""
+    old = hm.hamming_batch_config_get()
+    arena, descs, ys = _build_batch(300 + fine_log2 + 7 * schedule, 60)
+    expect = _expect(ys, descs)
+    n = descs.size
+    try:
+        hm.hamming_batch_config_set(schedule, 1, 0, use_graph)
+        full = _decode_with_workspace(gpu_device, arena, descs, hm.hamming_batch_workspace_bytes(n))
+        tiles = full.totals()["tiles"]
+        assert full.totals()["fine_log2"] == 0 and tiles >= 1 << fine_log2
+        _check_outputs(full, descs, expect, data_fill=0x77, ep_fill=0x88)
+        entries = (tiles >> fine_log2) + 1
+        ws = hm.hamming_batch_workspace_min_bytes(n) - 4 + 4 * entries
+        bd = _decode_with_workspace(gpu_device, arena, descs, ws)
+        assert bd.totals()["fine_log2"] == fine_log2 and bd.totals()["tiles"] == tiles
+        _check_outputs(bd, descs, expect, data_fill=0x77, ep_fill=0x88)
+    finally:
+        hm.hamming_batch_config_set(*old)
+
+
+@pytest.mark.parametrize("schedule", [0, 2, 3])
+@pytest.mark.parametrize("grid_cap", [0, 3])
+def test_batch_one_fine_entry_probes_across_many_packets(gpu_device, schedule, grid_cap):
+    """The smallest workspace (one fine entry) over 400 tiny and empty packets:
+    every wave probes from packet 0, through several 64-entry windows and over
+    runs of packets without tiles; with a grid cap the waves also loop."""
+    old = hm.hamming_batch_config_get()
+    rng = np.random.default_rng(400 + schedule)
+    sizes = [int(rng.choice([0, 0, 1, 5, 64, 127, 128, 129, 300])) for _ in range(400)]
+    rs = [int(rng.integers(3, 8)) for _ in range(400)]
+    arena, descs, ys = _build_batch(500 + schedule, 400, sizes=sizes, rs=rs)
+    expect = _expect(ys, descs)
+    try:
+        hm.hamming_batch_config_set(schedule, 1, grid_cap, 1)
+        bd = _decode_with_workspace(gpu_device, arena, descs, hm.hamming_batch_workspace_min_bytes(400))
+        t = bd.totals()
+        assert t["tiles"] > 64 and (t["tiles"] >> t["fine_log2"]) == 0
+        assert not bd.status[:400].cpu().numpy().any()
+        _check_outputs(bd, descs, expect, data_fill=0x77, ep_fill=0x88)
+    finally:
+        hm.hamming_batch_config_set(*old)
+
+
+def test_batch_workspace_below_minimum_is_rejected(gpu_device):
+    import torch
+
+    arena, descs, _ = _build_batch(600, 4)
+    cw = _to_dev(arena, gpu_device)
+    small = hm.hamming_batch_workspace_min_bytes(4) - 1
+    with pytest.raises(hm.HammingError) as e:
+        bd = hm.BatchDecoder(cw, 4, workspace_bytes=small)
+        bd.set_packets(descs)
+        bd.decode()
+    assert e.value.status == hm.HAMMING_ENOMEM
+    torch.cuda.synchronize()
+
+
+@pytest.fixture(scope="module")
+def full_batch(gpu_device):
     """The bench's batched workload at full size (20,000 packets, ~2.2e9
-    codewords) in the bench's launch configuration; sampled packets are
-    regenerated on the CPU from the same seeded streams, encoded and decoded
-    by the oracle, and compared with the batch output byte for byte."""
+    codewords: messages and flips drawn on the device by the seeded
+    generator, codewords from the library's encoder), decoded by one
+    hamming_decode_batch call in the bench's launch configuration; the outputs
+    come back to the host (about 17 GB)."""
     import os
     import sys
 
@@ -265,29 +346,67 @@ def test_batch_full_size_workload_sampled_packets(gpu_device):
     bd.set_packets(descs)
     bd.decode()
     torch.cuda.synchronize()
-    assert not bd.status[:n_packets].cpu().numpy().any()
+    status = bd.status[:n_packets].cpu().numpy()
+    data = bd.data.view(torch.uint8).cpu().numpy()
+    ep = bd.errpos.cpu().numpy()
+    del bd, arena
+    torch.cuda.empty_cache()
     _, _, p = synth.batch_packets(seed, n_packets)
-    # position of each packet inside its r's concatenated stream
+    # first codeword of each packet inside its r's generated stream
     pos = np.zeros(n_packets, dtype=np.int64)
     for rr in range(3, 8):
         idx = np.flatnonzero(r == rr)
         pos[idx] = np.concatenate([[0], np.cumsum(n_cw[idx])[:-1]])
+    return {"seed": seed, "descs": descs, "n_cw": n_cw, "r": r, "p": p, "pos": pos, "status": status,
+            "data": data, "errpos": ep}
+
+
+@pytest.mark.parametrize("rr", [3, 4, 5, 6, 7])
+def test_batch_full_size_every_packet_recovers_its_message(full_batch, rr):
+    """Every packet of code r of the full-size batch: each received word
+    carries at most one flip, so the exact decode is fixed without running a
+    decoder (a single-error-correcting code returns the sent message and names
+    the flipped position): the payload must equal the generator's message
+    stream for those codewords and errpos its flip positions (0 where none),
+    byte for byte.  Together with the oracle comparison below and the
+    encoder's own parity tests, this covers all 20,000 packets."""
+    fb = full_batch
+    assert not fb["status"].any()
+    sr = synth.subseed(fb["seed"], "r", rr)
+    for i in np.flatnonzero(fb["r"] == rr):
+        n, first = int(fb["n_cw"][i]), int(fb["pos"][i])
+        msg = synth.message_stream_slice(sr, first, n, rr).view(np.uint8)
+        p1, p2 = synth.error_positions(sr, n, rr, p_single=float(fb["p"][i]), start=first)
+        assert not p2.any()
+        o, e = int(fb["descs"][i]["data_word_off"]) * 8, int(fb["descs"][i]["errpos_off"])
+        assert np.array_equal(fb["data"][o:o + msg.size], msg), "packet %d (r=%d, n=%d)" % (i, rr, n)
+        assert np.array_equal(fb["errpos"][e:e + n], p1), "packet %d (r=%d, n=%d)" % (i, rr, n)
+
+
+def test_batch_full_size_oracle_on_small_and_sampled_packets(full_batch):
+    """The oracle on the full-size batch: every packet of at most 2^14
+    codewords (more than half of the 20,000) and 60 random larger ones plus
+    the largest and smallest of each r, regenerated on the CPU from the same
+    seeded streams, encoded by the oracle's encoder, decoded by the oracle and
+    compared with the batch output byte for byte."""
+    fb = full_batch
+    n_cw, r = fb["n_cw"], fb["r"]
     rng = np.random.default_rng(3)
-    sample = set(rng.choice(n_packets, size=80, replace=False).tolist())
+    large = np.flatnonzero(n_cw > (1 << 14))
+    sample = set(np.flatnonzero(n_cw <= (1 << 14)).tolist())
+    sample |= set(rng.choice(large, size=60, replace=False).tolist())
     for rr in range(3, 8):
         idx = np.flatnonzero(r == rr)
         sample.add(int(idx[np.argmax(n_cw[idx])]))
         sample.add(int(idx[np.argmin(n_cw[idx])]))
+    assert len(sample) > 10000
     for i in sorted(sample):
-        rr, n = int(r[i]), int(n_cw[i])
-        sr = synth.subseed(seed, "r", rr)
-        msg = synth.message_stream_slice(sr, int(pos[i]), n, rr)
+        rr, n, first = int(r[i]), int(n_cw[i]), int(fb["pos"][i])
+        sr = synth.subseed(fb["seed"], "r", rr)
+        msg = synth.message_stream_slice(sr, first, n, rr)
         cw = oracle.encode(msg, n, rr)
-        p1, p2 = synth.error_positions(sr, n, rr, p_single=float(p[i]), start=int(pos[i]))
+        p1, p2 = synth.error_positions(sr, n, rr, p_single=float(fb["p"][i]), start=first)
         d_ref, e_ref = oracle.decode(cw ^ synth.flip_masks(p1, p2, rr), rr)
-        o = int(descs[i]["data_word_off"]) * 8
-        e = int(descs[i]["errpos_off"])
-        d_gpu = bd.data.view(torch.uint8)[o:o + d_ref.size].cpu().numpy()
-        e_gpu = bd.errpos[e:e + n].cpu().numpy()
-        assert np.array_equal(d_gpu, d_ref), "packet %d (r=%d, n=%d)" % (i, rr, n)
-        assert np.array_equal(e_gpu, e_ref), "packet %d (r=%d, n=%d)" % (i, rr, n)
+        o, e = int(fb["descs"][i]["data_word_off"]) * 8, int(fb["descs"][i]["errpos_off"])
+        assert np.array_equal(fb["data"][o:o + d_ref.size], d_ref), "packet %d (r=%d, n=%d)" % (i, rr, n)
+        assert np.array_equal(fb["errpos"][e:e + n], e_ref), "packet %d (r=%d, n=%d)" % (i, rr, n)

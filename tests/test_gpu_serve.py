@@ -116,10 +116,11 @@ def test_serve_small_batches_under_every_batch_schedule(gpu_device, schedule):
         hm.hamming_batch_config_set(*old)
 
 
-def test_serve_large_batch_through_the_batch_graph(gpu_device):
-    """Batches above 16 requests go through hamming_decode_batch (descriptor
-    copy, plan, maps, decode) rather than the one-launch small-batch form the
-    other tests exercise; the results must be the same."""
+def test_serve_large_batch_through_the_host_plan(gpu_device):
+    """Batches above 16 requests are planned on the host (prefix sums and a
+    coarse tile map copied with the descriptors, then one decode launch)
+    rather than the one-launch small-batch form the other tests exercise;
+    the results must be the same."""
     rng = np.random.default_rng(11)
     n = 40
     sizes = [int(rng.choice([0, 1, 63, 64, 65, 300, 4097])) for _ in range(n)]
@@ -238,3 +239,121 @@ def test_serve_open_loop_trace(gpu_device):
         assert srv.stats()["output_bytes_used"] == 0
     finally:
         srv.close()
+
+
+@pytest.fixture(scope="module")
+def trace_pool(gpu_device):
+    """A codeword pool like the serving trace's, built on the CPU (seeded
+    messages, the oracle's encoder, 10% single flips): one segment of 2^21
+    codewords per r = 4, 5, 6 and 2^20 for r = 7; plus the plain decoder's
+    measured rate on each segment."""
+    import torch
+
+    segs, base, off = [], {}, 0
+    for r in (4, 5, 6, 7):
+        n = 1 << (20 if r == 7 else 21)
+        y = received_words(synth.workload_seed("serve-trace", r), n, r, p_single=0.1)
+        base[r] = (off, n)
+        segs.append(y)
+        off += y.size
+    host = np.concatenate(segs + [np.zeros(2, dtype=np.uint64)])
+    cw = _to_dev(host, gpu_device)
+    rate = {}
+    for r, (o, n) in base.items():
+        wpc = hm.words_per_codeword(r)
+        seg = cw[o:o + n * wpc]
+        data = torch.empty(hm.hamming_data_bytes(n, r), dtype=torch.uint8, device=gpu_device)
+        ep = torch.empty(n, dtype=torch.uint8, device=gpu_device)
+        times = []
+        for _ in range(6):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            hm.hamming_decode(seg, n, r, data, ep)
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b) * 1e-3)
+        rate[r] = n * hm.hamming_message_bits(r) / sorted(times)[3]      # payload bits per second
+    return host, cw, base, rate
+
+
+@pytest.mark.parametrize("rho", [0.7, 0.9])
+def test_serve_trace_scale_results_alone_mix_and_oracle(gpu_device, trace_pool, rho):
+    """The serving trace's shape: 256 SDR streams (stream s decodes r = 4 +
+    s % 4), request sizes log-uniform in [256, 2^18] codewords, Poisson
+    arrivals at 70% and 90% of the plain decoder's measured rate on the mix, 4
+    batches in flight of at most 4,096 requests and 2^25 codewords.  Outputs
+    stay resident (auto_release off), so every one of the 6,000 requests is
+    compared with a plain decode of the same codewords alone, and 400 random
+    ones with the oracle."""
+    import torch
+
+    host, cw, base, rate = trace_pool
+    rng = np.random.default_rng(int(rho * 100))
+    n = 6000
+    stream_id = rng.integers(0, 256, size=n)
+    rs = (4 + stream_id % 4).astype(np.uint32)
+    sizes = np.floor(256 * np.exp2(10 * rng.random(n))).astype(np.uint64)
+    offs = np.empty(n, dtype=np.uint64)
+    for r, (o, seg_n) in base.items():
+        m = rs == r
+        offs[m] = np.uint64(o) + np.floor(rng.random(m.sum()) * (seg_n - sizes[m])).astype(np.uint64) * \
+            np.uint64(hm.words_per_codeword(r))
+    t_plain = np.array([float(sz) * hm.hamming_message_bits(int(r)) / rate[int(r)] for sz, r in zip(sizes, rs)])
+    arrivals = (np.cumsum(rng.exponential(t_plain.mean() / rho, size=n)) * 1e9).astype(np.uint64)
+    out_bytes = sum((((hm.hamming_data_bytes(int(sz), int(r)) + 15) // 16 * 16 + int(sz) + 255) // 256) * 256
+                    for sz, r in zip(sizes, rs))
+    srv = hm.Server(cw, slots=4, max_batch_packets=4096, max_batch_codewords=1 << 25,
+                    output_pool_bytes=out_bytes + (1 << 20), auto_release=False)
+    try:
+        lat, _ = srv.run_trace(arrivals, offs, sizes, rs, timeout_s=60)
+        assert (lat > 0).all()
+        got = {}
+        for c in srv.poll(max_n=2 * n):
+            got[c.request_id] = c
+        assert len(got) == n and all(c.status == 0 for c in got.values())
+        assert srv.stats()["batches"] < n          # requests were batched together
+        ids = sorted(got)
+        check = set(rng.choice(n, size=400, replace=False).tolist())
+        for i, rid in enumerate(ids):
+            r, sz, o = int(rs[i]), int(sizes[i]), int(offs[i])
+            wpc = hm.words_per_codeword(r)
+            d_mix, e_mix = srv.result(got[rid], r, sz)
+            d_alone, e_alone = hm.decode(cw[o:o + sz * wpc], r)
+            assert torch.equal(d_mix, d_alone) and torch.equal(e_mix, e_alone), "request %d" % i
+            if i in check:
+                d_ref, e_ref = oracle.decode(host[o:o + sz * wpc], r)
+                assert np.array_equal(d_mix.cpu().numpy(), d_ref), "request %d" % i
+                assert np.array_equal(e_mix.cpu().numpy(), e_ref), "request %d" % i
+        for rid in ids:
+            srv.release(rid)
+        assert srv.stats()["output_bytes_used"] == 0
+    finally:
+        srv.close()
+
+
+@pytest.mark.parametrize("schedule", [0, 1, 2, 3])
+def test_serve_host_plan_many_packets_every_schedule(gpu_device, schedule):
+    """Large host-planned batches (hundreds of requests, several with no
+    codewords) whose coarse map groups several tiles per entry, under every
+    batch schedule."""
+    rng = np.random.default_rng(70 + schedule)
+    n = 600
+    sizes = [int(rng.choice([0, 1, 63, 64, 65, 300, 1000, 4097, 30000])) for _ in range(n)]
+    rs = [int(rng.integers(3, 8)) for _ in range(n)]
+    pool, offs, ys = _pool(30 + schedule, sizes, rs)
+    cw = _to_dev(pool, gpu_device)
+    old = hm.hamming_batch_config_get()
+    hm.hamming_batch_config_set(schedule, 8, 0, old[3])
+    srv = hm.Server(cw, slots=2, max_batch_packets=300, max_batch_codewords=1 << 30, output_pool_bytes=1 << 30)
+    try:
+        ids = {srv.submit(offs[i], sizes[i], rs[i]): i for i in range(n)}
+        got = _drain(srv, n)
+        assert srv.stats()["batches"] == 2
+        for rid, c in got.items():
+            i = ids[rid]
+            if sizes[i]:
+                _check_request(srv, c, ys[i], rs[i], cw, offs[i])
+            srv.release(rid)
+    finally:
+        srv.close()
+        hm.hamming_batch_config_set(*old)
