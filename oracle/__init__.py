@@ -47,8 +47,10 @@ def _load():
     global _lib
     with _lock:
         if _lib is None:
-            build()
-            lib = ctypes.CDLL(_LIB_PATH)
+            # ORACLE_LIB names another build of the same sources (the
+            # sanitizer build of the CPU test suite)
+            path = os.environ.get("ORACLE_LIB") or build()
+            lib = ctypes.CDLL(path)
             u64, i32, vp = ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p
             lib.oracle_code_n.argtypes = [i32]
             lib.oracle_code_n.restype = i32

@@ -132,14 +132,17 @@ def packet_dtype():
 
 
 def library() -> ctypes.CDLL:
-    """Load libhamming.so from the package directory (raises if missing)."""
+    """Load libhamming.so from the package directory (raises if missing).
+    HAMMING_LIB may name another build of the same sources (the sanitizer
+    build of the CPU test suite)."""
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(LIB_PATH):
-                raise ImportError("libhamming.so is not built (run paper_1412_6862_amd/build.py); "
-                                  "there is no fallback decoder")
-            lib = ctypes.CDLL(LIB_PATH)
+            path = os.environ.get("HAMMING_LIB") or LIB_PATH
+            if not os.path.exists(path):
+                raise ImportError("%s is not built (run paper_1412_6862_amd/build.py); "
+                                  "there is no fallback decoder" % path)
+            lib = ctypes.CDLL(path)
             for name, (args, res) in _SIGNATURES.items():
                 fn = getattr(lib, name)
                 fn.argtypes = args

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "hamming.h"
+#include "host_plan.h"
 
 namespace hm {
 
@@ -137,9 +138,6 @@ struct PlannedBatch {
     uint32_t xcd_chunk;
     uint32_t reserved;
 };
-
-// Coarse-map entries a host plan of n packets may use.
-inline uint64_t planned_coarse_capacity(uint32_t n) { return 2ull * n + 64; }
 
 // Bytes of a host plan of n packets: prefix sums, coarse map (padded to 8
 // bytes), descriptors.

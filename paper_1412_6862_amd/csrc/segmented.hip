@@ -24,8 +24,14 @@
 
 #include "hamming.h"
 #include "launch.h"
+#include "seg_bits.h"
 #include "tile.h"
 
+using hm::funnel128;
+using hm::head_expand;
+using hm::head_message;
+using hm::mask_top;
+using hm::run_start;
 using hm::wave_sync;
 
 namespace {
@@ -113,34 +119,6 @@ struct WindowWalk {
     }
 };
 
-// Index, within its segment, of the first message bit of window v, and pw =
-// 1 when position 128v is a checksum position.  For v >= 1 that can only be
-// 128v itself (when v is a power of two), so the window's message bits are
-// consecutive from position 128v + pw, whose message index is 128v + pw minus
-// the floor(log2 v) + 8 checksum positions below it minus one.  Window 0
-// starts at message bit 0.
-__device__ __forceinline__ uint32_t run_start(uint32_t v, uint32_t& pw)
-{
-    const uint32_t lv = 31u - __clz(v | 1u);
-    pw = (v & (v - 1u)) == 0u ? 1u : 0u;
-    return v == 0 ? 0u : 128u * v + pw - lv - 9u;
-}
-
-// 128 bits starting at bit s (0..63) of word a, continuing into b and c.
-__device__ __forceinline__ void funnel128(uint64_t a, uint64_t b, uint64_t c, uint32_t s, uint64_t& lo, uint64_t& hi)
-{
-    lo = (a >> s) | ((b << 1) << (63u - s));
-    hi = (b >> s) | ((c << 1) << (63u - s));
-}
-
-// Keeps positions 0..top of a window (top = last position of the segment
-// minus 128v).
-__device__ __forceinline__ void mask_top(uint64_t& x0, uint64_t& x1, uint32_t top)
-{
-    x0 &= ~uint64_t(0) >> (63u - min(top, 63u));
-    x1 &= top < 64u ? uint64_t(0) : (~uint64_t(0) >> (63u - min(top - 64u, 63u)));
-}
-
 // ORs 128 bits into a word array at word bq, bit bs (three LDS atomics:
 // neighbouring threads' runs share the boundary words).
 __device__ __forceinline__ void or128(uint64_t* W, uint32_t bq, uint32_t bs, uint64_t x0, uint64_t x1)
@@ -186,22 +164,6 @@ __device__ __forceinline__ void flush_partial(uint64_t* X, uint32_t* H, uint32_t
         atomicXor(reinterpret_cast<unsigned long long*>(&X[i]), x);
         atomicXor(&H[i], h);
     }
-}
-
-// The message positions below 64 (3, 5..7, 9..15, 17..31, 33..63) carry a
-// segment's first 57 message bits.  head_message compacts them from positions
-// 1..64 given as bits 0..63; head_expand places message bits 0..56 at those
-// positions given as bits 0..63 of window 0 (position q at bit q).
-__device__ __forceinline__ uint64_t head_message(uint64_t w)
-{
-    return ((w >> 2) & 0x1ull) | (((w >> 4) & 0x7ull) << 1) | (((w >> 8) & 0x7Full) << 4) |
-           (((w >> 16) & 0x7FFFull) << 11) | (((w >> 32) & 0x7FFFFFFFull) << 26);
-}
-
-__device__ __forceinline__ uint64_t head_expand(uint64_t m)
-{
-    return ((m & 0x1ull) << 3) | (((m >> 1) & 0x7ull) << 5) | (((m >> 4) & 0x7Full) << 9) |
-           (((m >> 11) & 0x7FFFull) << 17) | (((m >> 26) & 0x7FFFFFFFull) << 33);
 }
 
 // Barrier of the threads that work on one packet: part of a wave or one wave

@@ -30,6 +30,8 @@
 
 #include "batch.h"
 #include "hamming.h"
+#include "host_plan.h"
+#include "ring_alloc.h"
 
 namespace {
 
@@ -63,54 +65,6 @@ struct Request {
     uint8_t state;
 };
 
-// Circular allocator over [0, size): allocations are handed out and
-// reclaimed in the same (FIFO) order.  head == tail with live allocations
-// means full.
-class RingAllocator {
-public:
-    explicit RingAllocator(uint64_t size = 0) : size_(size) {}
-
-    bool alloc(uint64_t bytes, uint64_t* off)
-    {
-        if (live_ == 0) head_ = tail_ = 0;
-        if (bytes == 0 || bytes > size_) return false;
-        if (live_ == 0 || head_ > tail_) {              // free space: [head, size) and [0, tail)
-            if (size_ - head_ >= bytes) {
-                *off = head_;
-                head_ += bytes;
-            } else if (tail_ >= bytes) {                // wrap; [head, size) is skipped
-                *off = 0;
-                head_ = bytes;
-            } else {
-                return false;
-            }
-        } else {                                        // wrapped: free space is [head, tail)
-            if (tail_ - head_ < bytes) return false;
-            *off = head_;
-            head_ += bytes;
-        }
-        ++live_;
-        used_ += bytes;
-        return true;
-    }
-
-    // Reclaim the oldest live allocation.
-    void release_oldest(uint64_t off, uint64_t bytes)
-    {
-        tail_ = off + bytes;
-        --live_;
-        used_ -= bytes;
-        if (live_ == 0) head_ = tail_ = 0;
-    }
-
-    uint64_t size() const { return size_; }
-    uint64_t used() const { return used_; }
-
-private:
-    uint64_t size_;
-    uint64_t head_ = 0, tail_ = 0, used_ = 0, live_ = 0;
-};
-
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
@@ -127,7 +81,7 @@ struct hamming_server {
     const uint64_t* pool = nullptr;
     uint64_t pool_words = 0;
     unsigned char* out_base = nullptr;
-    RingAllocator alloc;
+    hm::RingAllocator alloc;
     std::vector<Slot> slots;
     std::vector<Request> ring;         // request id -> ring[id % ring.size()]
     uint64_t next_id = 0;              // ids [next_admit, next_id) are queued
@@ -241,15 +195,9 @@ int launch_planned(hamming_server* s, Slot& sl, uint32_t n, int schedule, uint32
     const uint64_t total = ts[n];
     if (total == 0) return HAMMING_OK;
     // entry j = the packet holding tile j << g, at most planned_coarse_capacity(n) entries
-    const uint64_t cap = hm::planned_coarse_capacity(n);
-    uint32_t g = 0;
-    while ((total >> g) >= cap) ++g;
-    const uint64_t entries = (total + (uint64_t(1) << g) - 1) >> g;
+    const uint32_t g = hm::planned_coarse_log2(total, n);
     const uint64_t coarse_off = ts_off + 8ull * (n + 1);
-    auto* coarse = reinterpret_cast<uint32_t*>(sl.plan_host + coarse_off);
-    uint64_t j = 0;
-    for (uint32_t p = 0; p < n && j < entries; ++p)
-        while (j < entries && (j << g) < ts[p + 1]) coarse[j++] = p;
+    const uint64_t entries = hm::plan_coarse_map(ts, n, g, reinterpret_cast<uint32_t*>(sl.plan_host + coarse_off));
     const uint64_t bytes = coarse_off + 4 * entries;
     if (hipMemcpyAsync(sl.plan_dev, sl.plan_host, bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
         return HAMMING_EDEVICE;
@@ -368,7 +316,7 @@ int hamming_server_create(const hamming_server_config* config, const uint64_t* c
     s->pool = cw_pool;
     s->pool_words = cw_pool_words;
     s->out_base = static_cast<unsigned char*>(output_pool);
-    s->alloc = RingAllocator(output_pool_bytes / kAlign * kAlign);
+    s->alloc = hm::RingAllocator(output_pool_bytes / kAlign * kAlign);
     try {
         // queued + in flight + completed but not yet released
         s->ring.resize(uint64_t(c.max_queue) + uint64_t(c.slots) * c.max_batch_packets);
