@@ -429,12 +429,16 @@ int hamming_decode_host(const uint64_t *host_cw, uint64_t n_cw, int r, void *hos
 /*
  * Autotuner: on the current device and `stream`, time the plain decode of
  * random 2^26-codeword packets (2^25 for r = 7) for every lane width and XCD
- * chunking, and the batched decode of a 500-packet batch of mixed sizes and r
- * for every schedule and XCD chunking; apply the fastest shapes (as
- * hamming_plain_config_set / hamming_batch_config_set would) and, when
- * cache_path is neither NULL nor empty, write them there.  flags: bit 0 tunes
- * the plain decode, bit 1 the batched decode.  Allocates about 1.1 GB of
- * device memory for the duration of the call and synchronises `stream`.
+ * chunking, and the batched decode of a batch of up to 2,000 packets (sizes
+ * log-uniform in [64, 2^20] codewords, r uniform in 3..7, packed into a
+ * 2^28-word (2 GiB) codeword arena) for every schedule and XCD chunking;
+ * apply the fastest shapes (as hamming_plain_config_set /
+ * hamming_batch_config_set would) and, when cache_path is neither NULL nor
+ * empty, write them there.  flags: bit 0 tunes the plain decode, bit 1 the
+ * batched decode.  Allocates up to about 5 GB of device memory for the
+ * duration of the call (1.1 GB for the plain trials, the batch arena and its
+ * outputs) and synchronises `stream`.  The cache is keyed by the device
+ * architecture only: shapes tuned on this batch serve every later batch.
  * Returns HAMMING_OK, HAMMING_EINVAL, HAMMING_ENOMEM or HAMMING_EDEVICE.
  */
 int hamming_tune(const char *cache_path, uint32_t flags, hipStream_t stream);
