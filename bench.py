@@ -793,6 +793,8 @@ def main() -> int:
                     help="serving leg: at most 2^L codewords per batch")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner before timing instead of loading the committed shapes")
+    ap.add_argument("--tune-out", default="", metavar="PATH",
+                    help="with --tune: also write the tuned shapes to PATH (the format of tuned_shapes.json)")
     ap.add_argument("--seg-packets", type=int, default=1 << 19)
     ap.add_argument("--seg-shapes", default="",
                     help="segmented leg: comma-separated M/t shapes (e.g. 1200/4); default the Table 1 grid")
@@ -824,7 +826,7 @@ def main() -> int:
     hm.library()
     legs = set(args.legs.split(","))
     if args.tune:
-        hm.hamming_tune(None, 3)
+        hm.hamming_tune(args.tune_out or None, 3)
     elif os.path.exists(TUNED_SHAPES):
         try:
             hm.hamming_tune_load(TUNED_SHAPES)

@@ -9,7 +9,11 @@
 // positions 32q+b+1 for the same b share bits 0..4, so for j <= 4 the dwords
 // are XOR-folded first and bit j is the parity of (fold & M_j).  Bits 5 and 6
 // depend on which dword a bit came from and are taken from explicit
-// high/low-bit selections.  Parity is popcount & 1 (v_bcnt_u32_b32).
+// high/low-bit selections.  Parity is the low bit of a popcount
+// (v_bcnt_u32_b32); the parities are gathered by a funnel shift that moves
+// each one in as the new top bit of an accumulator (v_alignbit_b32), so bit j
+// needs no masking or shifting of its own and stale low bits fall out at the
+// end.
 //
 // Correction (Sec. II, error correction unit): the checksum value s names the
 // flipped position; storage bit s-1 is inverted, branch-free, when s != 0.
@@ -42,23 +46,28 @@ __device__ constexpr uint32_t kSetMask4 = 0x7FFF8000u;
 constexpr uint32_t kTop = 0x80000000u;
 constexpr uint32_t kLow31 = 0x7FFFFFFFu;
 
-__device__ __forceinline__ uint32_t par(uint32_t x) { return __builtin_popcount(x) & 1u; }
-
 __device__ __forceinline__ uint32_t bfe(uint32_t x, int off, int len)
 {
     return (x >> off) & ((len >= 32) ? 0xFFFFFFFFu : ((1u << len) - 1u));
 }
 
-// Checksum bits 0..J-1 of a folded dword (J <= 5).
-template <int J>
-__device__ __forceinline__ uint32_t low_checksum(uint32_t f)
+// acc >> 1 with the parity of x as the new bit 31.  After J pushes, bits
+// 32-J .. 31 hold the J parities in push order (first pushed lowest).
+__device__ __forceinline__ uint32_t push_parity(uint32_t acc, uint32_t x)
 {
-    uint32_t s = par(f & kSetMask0);
-    if constexpr (J > 1) s |= par(f & kSetMask1) << 1;
-    if constexpr (J > 2) s |= par(f & kSetMask2) << 2;
-    if constexpr (J > 3) s |= par(f & kSetMask3) << 3;
-    if constexpr (J > 4) s |= par(f & kSetMask4) << 4;
-    return s;
+    return __builtin_amdgcn_alignbit(uint32_t(__builtin_popcount(x)), acc, 1);
+}
+
+// Push checksum bits 0..J-1 of a folded dword (J <= 5).
+template <int J>
+__device__ __forceinline__ uint32_t push_low_checksum(uint32_t acc, uint32_t f)
+{
+    acc = push_parity(acc, f & kSetMask0);
+    if constexpr (J > 1) acc = push_parity(acc, f & kSetMask1);
+    if constexpr (J > 2) acc = push_parity(acc, f & kSetMask2);
+    if constexpr (J > 3) acc = push_parity(acc, f & kSetMask3);
+    if constexpr (J > 4) acc = push_parity(acc, f & kSetMask4);
+    return acc;
 }
 
 // Clear the padding bits (storage bits >= n) of a codeword.
@@ -80,22 +89,22 @@ template <int R>
 __device__ __forceinline__ uint32_t checksum(const uint32_t (&a)[Code<R>::DW])
 {
     if constexpr (R <= 5) {
-        return low_checksum<R>(a[0]);
+        return push_low_checksum<R>(0u, a[0]) >> (32 - R);
     } else if constexpr (R == 6) {
-        uint32_t s = low_checksum<5>(a[0] ^ a[1]);
+        uint32_t acc = push_low_checksum<5>(0u, a[0] ^ a[1]);
         // positions 32..63: bit 31 of dword 0 and bits 0..30 of dword 1
         // (dword 1's bit 31 is padding and already clear)
-        s |= par((a[0] & kTop) | a[1]) << 5;
-        return s;
+        acc = push_parity(acc, (a[0] & kTop) | a[1]);
+        return acc >> 26;
     } else {
-        uint32_t s = low_checksum<5>(a[0] ^ a[1] ^ a[2] ^ a[3]);
+        uint32_t acc = push_low_checksum<5>(0u, a[0] ^ a[1] ^ a[2] ^ a[3]);
         // bit 5: positions 32, 33..63, 96, 97..127
         const uint32_t h = a[0] ^ a[2];
         const uint32_t l = a[1] ^ a[3];
-        s |= par((h & kTop) | (l & kLow31)) << 5;
+        acc = push_parity(acc, (h & kTop) | (l & kLow31));
         // bit 6: positions 64..127
-        s |= par(a[2] ^ a[3] ^ (a[1] & kTop)) << 6;
-        return s;
+        acc = push_parity(acc, a[2] ^ a[3] ^ (a[1] & kTop));
+        return acc >> 25;
     }
 }
 

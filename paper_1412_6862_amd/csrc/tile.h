@@ -157,6 +157,26 @@ __device__ __forceinline__ void load_tile(const uint64_t* __restrict__ cw, uint6
     }
 }
 
+// Issue the loads of a tile known to be full, from a 16-byte aligned packet
+// (the vector form of load_tile with no checks).
+template <int R, int U>
+__device__ __forceinline__ void load_full_tile(const uint64_t* __restrict__ cw, uint64_t tile, TileIn<R, U>& t)
+{
+    using C = Code<R>;
+    using T = TileShape<R, U>;
+    const uint32_t lane = threadIdx.x & 63u;
+    t.coalesced = true;
+    const u32x4* src = reinterpret_cast<const u32x4*>(cw + tile * T::CW * C::WPC) + lane;
+#pragma unroll
+    for (int v = 0; v < T::NV; ++v) {
+        const u32x4 x = __builtin_nontemporal_load(src + 64 * v);
+        t.in[4 * v + 0] = x.x;
+        t.in[4 * v + 1] = x.y;
+        t.in[4 * v + 2] = x.z;
+        t.in[4 * v + 3] = x.w;
+    }
+}
+
 // Decode the loaded codewords of tile `tile` and write its outputs.
 template <int R, int U>
 __device__ __forceinline__ void finish_tile(TileIn<R, U>& tin, uint64_t n_cw, uint64_t tile,

@@ -80,6 +80,10 @@ std::string device_name()
 }
 
 constexpr uint32_t kXcdChoices[] = {1, 8, 32, 128};
+// Plain grid caps in workgroups: 0 is one wave per tile; the others make the
+// waves loop over the packet, two tiles in flight per wave (256 CUs hold
+// 2048 workgroups at 8 waves per SIMD).
+constexpr uint64_t kPlainGridChoices[] = {0, 1024, 2048, 4096};
 
 }  // namespace
 
@@ -115,16 +119,18 @@ int hamming_tune(const char* cache_path, uint32_t flags, hipStream_t stream)
         float best = 1e30f;
         for (int u : {2, 4, 8, 16}) {
             for (uint32_t xc : kXcdChoices) {
-                if (hamming_plain_config_set(r, u, 0, xc) != HAMMING_OK) continue;   // invalid lane width
-                float ms = 0;
-                const int rc = time_ms(stream, 2, 5, [&] {
-                    return hamming_decode(static_cast<const uint64_t*>(cw.p), n, r, data.p,
-                                          static_cast<uint8_t*>(ep.p), stream);
-                }, &ms);
-                if (rc != HAMMING_OK) return rc;
-                if (ms < best) {
-                    best = ms;
-                    plain[r - 3] = {u, 0, xc, ms * 1000.0f};
+                for (uint64_t mb : kPlainGridChoices) {
+                    if (hamming_plain_config_set(r, u, mb, xc) != HAMMING_OK) continue;   // invalid lane width
+                    float ms = 0;
+                    const int rc = time_ms(stream, 2, 5, [&] {
+                        return hamming_decode(static_cast<const uint64_t*>(cw.p), n, r, data.p,
+                                              static_cast<uint8_t*>(ep.p), stream);
+                    }, &ms);
+                    if (rc != HAMMING_OK) return rc;
+                    if (ms < best) {
+                        best = ms;
+                        plain[r - 3] = {u, mb, xc, ms * 1000.0f};
+                    }
                 }
             }
         }

@@ -65,6 +65,21 @@ def test_plain_every_lane_shape_and_grid_cap(gpu_device, r):
         hm.hamming_plain_config_set(r, *old)
 
 
+@pytest.mark.parametrize("r", [3, 4, 5, 6, 7])
+def test_plain_looping_grid_large_ragged(gpu_device, r):
+    # grids far smaller than the packet: every wave decodes many full tiles
+    # with the next tile's loads in flight, then one wave takes the ragged tail
+    old = hm.hamming_plain_config_get(r)
+    n_cw = 300_013
+    y = received_words(synth.workload_seed("gpu-loop", r), n_cw, r, p_single=0.3, p_double=0.05)
+    try:
+        for cap, chunk in ((5, 1), (37, 2), (256, 8), (2048, 32)):
+            hm.hamming_plain_config_set(r, hm.hamming_plain_config_get(r)[0], cap, chunk)
+            _check(y, r, gpu_device)
+    finally:
+        hm.hamming_plain_config_set(r, *old)
+
+
 @pytest.mark.parametrize("r", [3, 6, 7])
 def test_plain_unaligned_input_and_errpos(gpu_device, r):
     import torch
