@@ -257,6 +257,36 @@ uint64_t hamming_decode_batch_grid(uint64_t cw_words, uint32_t max_packets, uint
  * HAMMING_OK or HAMMING_EDEVICE. */
 int hamming_batch_release_graphs(void);
 
+/*
+ * For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the batched
+ * decode of hamming_decode_batch, with the same arguments, results, per-packet
+ * status and kernels, but with its workspace taken from a fixed device array
+ * of HAMMING_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs
+ * on until the process ends.  The call itself allocates nothing: no
+ * hipMalloc, no hipFree, no graph instantiation (the kernels are launched
+ * directly on `stream`, so a capturing stream records them).  The first call
+ * on a device looks up that device's copy of the array once.
+ *   max_packets : at most HAMMING_NOALLOC_MAX_PACKETS (HAMMING_ERANGE above).
+ *                 The tile-to-packet map gets what the array holds beyond the
+ *                 prefix sums; a batch with more tiles than map entries
+ *                 decodes through the probe path (slower, same results).
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (nothing in it needs to start at zero: each call writes the prefix
+ * sums and maps before reading them).  Calls that overlap in time on one GPU
+ * (on different streams, or from several host threads) race on the array and
+ * may decode wrongly; serialise them, for example on one stream.
+ * Returns HAMMING_OK, HAMMING_EINVAL, HAMMING_EALIGN, HAMMING_ERANGE or
+ * HAMMING_EDEVICE (also when the array's address cannot be looked up).
+ */
+#define HAMMING_NOALLOC_MAX_PACKETS 65536u
+#define HAMMING_NOALLOC_SCRATCH_BYTES (4u << 20)
+int hamming_decode_batch_noalloc(const uint64_t *cw_arena, uint64_t cw_words,
+                                 const hamming_packet *descs, const uint32_t *n_packets_dev,
+                                 uint32_t max_packets, uint64_t max_codewords, uint64_t *data_arena,
+                                 uint64_t data_words, uint8_t *errpos_arena, uint64_t errpos_bytes,
+                                 int32_t *status_out, hipStream_t stream);
+
 /* ---- bit-plane input layout -------------------------------------------------
  *
  * The index-set clustering of Sec. III.A (Fig. 4) carried to single

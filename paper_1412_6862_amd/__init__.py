@@ -55,6 +55,8 @@ _SIGNATURES = {
     "hamming_batch_release_graphs": ([], _i32),
     "hamming_decode_batch": ([_vp, _u64, _vp, _vp, ctypes.c_uint32, _u64, _vp, _u64, _vp, _u64, _vp, _vp, _u64,
                               _vp], _i32),
+    "hamming_decode_batch_noalloc": ([_vp, _u64, _vp, _vp, ctypes.c_uint32, _u64, _vp, _u64, _vp, _u64, _vp,
+                                      _vp], _i32),
     "hamming_batch_config_set": ([_i32, ctypes.c_uint32, ctypes.c_uint32, _i32], _i32),
     "hamming_batch_config_get": ([ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_uint32),
                                   ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_i32)], _i32),
@@ -259,6 +261,20 @@ def hamming_decode_batch(cw_arena, cw_words: int, descs, n_packets_dev, max_pack
                                           _ptr(errpos_arena),
                                           errpos_bytes, _ptr(status_out), _ptr(workspace), workspace_bytes,
                                           _stream(stream)), "hamming_decode_batch")
+
+
+def hamming_decode_batch_noalloc(cw_arena, cw_words: int, descs, n_packets_dev, max_packets: int,
+                                 max_codewords: int, data_arena, data_words: int, errpos_arena, errpos_bytes: int,
+                                 status_out, stream=None) -> None:
+    """Enqueue ``hamming_decode_batch_noalloc`` (device tensors or raw pointers)."""
+    _check(library().hamming_decode_batch_noalloc(_ptr(cw_arena), cw_words, _ptr(descs), _ptr(n_packets_dev),
+                                                  max_packets, max_codewords, _ptr(data_arena), data_words,
+                                                  _ptr(errpos_arena), errpos_bytes, _ptr(status_out),
+                                                  _stream(stream)), "hamming_decode_batch_noalloc")
+
+
+HAMMING_NOALLOC_MAX_PACKETS = 65536
+HAMMING_NOALLOC_SCRATCH_BYTES = 4 << 20
 
 
 def hamming_batch_config_set(schedule: int, xcd_chunk: int = 1, grid_cap_blocks: int = 0,

@@ -45,7 +45,7 @@ struct BatchArgs {
     uint32_t fine_blocks;   // grid of the fine-map kernel (it loops over entries beyond the grid)
 };
 
-inline uint32_t batch_coarse_capacity(uint32_t max_packets) { return 2 * max_packets + 1024; }
+constexpr uint32_t batch_coarse_capacity(uint32_t max_packets) { return 2 * max_packets + 1024; }
 
 // Fine-map entries of the recommended workspace: one per tile of batches up
 // to 2^24 tiles (or 4 per packet), so the map is exact for every usual batch.
@@ -55,13 +55,13 @@ inline uint32_t batch_fine_capacity_full(uint32_t max_packets)
 }
 
 // Workspace bytes before the fine map: header, tile prefix sums, coarse map.
-inline uint64_t batch_workspace_fixed_bytes(uint32_t max_packets)
+constexpr uint64_t batch_workspace_fixed_bytes(uint32_t max_packets)
 {
     return sizeof(BatchWs) + 8ull * (uint64_t(max_packets) + 1) + 4ull * batch_coarse_capacity(max_packets);
 }
 
 // Smallest workspace a call accepts: the fixed part plus one fine entry.
-inline uint64_t batch_workspace_min_bytes(uint32_t max_packets) { return batch_workspace_fixed_bytes(max_packets) + 4; }
+constexpr uint64_t batch_workspace_min_bytes(uint32_t max_packets) { return batch_workspace_fixed_bytes(max_packets) + 4; }
 
 // Recommended workspace (hamming_batch_workspace_bytes).
 inline uint64_t batch_workspace_bytes(uint32_t max_packets)

@@ -76,6 +76,35 @@ hipGraphExec_t find_or_capture(const GraphKey& key, hipStream_t stream)
     return exec;
 }
 
+// Workspace of hamming_decode_batch_noalloc: one copy per GPU, held by the
+// library's code object until the process ends.  Host code must not use this
+// name as an address (it is a host-side stand-in); scratch_address() gives
+// the current device's copy.
+static __device__ __align__(256) uint8_t scratch[HAMMING_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+std::atomic<void*> g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on device `dev` (the current device), looked up
+// on the first call for that device; nullptr when the lookup fails.
+void* scratch_address(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    void* p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+    if (p) return p;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+    if (!p) {
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev].store(p, std::memory_order_release);
+    }
+    return p;
+}
+
 bool misaligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) != 0; }
 
 // Upper bound on the tiles of any batch the arguments allow: the input arena
@@ -240,6 +269,28 @@ int hamming_decode_batch(const uint64_t* cw_arena, uint64_t cw_words, const hamm
         if (exec) return hipGraphLaunch(exec, stream) == hipSuccess ? HAMMING_OK : HAMMING_EDEVICE;
     }
     return hm::launch_batch(a, schedule, grid, stream) == hipSuccess ? HAMMING_OK : HAMMING_EDEVICE;
+}
+
+int hamming_decode_batch_noalloc(const uint64_t* cw_arena, uint64_t cw_words, const hamming_packet* descs,
+                                 const uint32_t* n_packets_dev, uint32_t max_packets, uint64_t max_codewords,
+                                 uint64_t* data_arena, uint64_t data_words, uint8_t* errpos_arena,
+                                 uint64_t errpos_bytes, int32_t* status_out, hipStream_t stream)
+{
+    if (max_packets > HAMMING_NOALLOC_MAX_PACKETS) return HAMMING_ERANGE;
+    if (max_packets == 0) return HAMMING_OK;
+    static_assert(HAMMING_NOALLOC_SCRATCH_BYTES >= hm::batch_workspace_min_bytes(HAMMING_NOALLOC_MAX_PACKETS),
+                  "the scratch array must hold the workspace of the largest batch it accepts");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HAMMING_EDEVICE;
+    void* ws = scratch_address(dev);
+    if (!ws) return HAMMING_EDEVICE;
+    BatchArgs a;
+    uint32_t grid = 0;
+    const int rc = hm::batch_prepare(cw_arena, cw_words, descs, n_packets_dev, max_packets, max_codewords, data_arena,
+                                     data_words, errpos_arena, errpos_bytes, status_out, ws,
+                                     HAMMING_NOALLOC_SCRATCH_BYTES, &a, &grid);
+    if (rc != HAMMING_OK) return rc;
+    return hm::launch_batch(a, g_schedule.load(), grid, stream) == hipSuccess ? HAMMING_OK : HAMMING_EDEVICE;
 }
 
 int hamming_batch_release_graphs(void)

@@ -147,6 +147,23 @@ def test_batch_workspace_and_validation_codes():
     assert call(wsb=0) == hm.HAMMING_ENOMEM
 
 
+def test_noalloc_batch_limits_and_host_side_codes():
+    # the binding's constants are the header's, and the fixed scratch holds the
+    # workspace of the largest batch the call accepts
+    text = open(os.path.join(ROOT, "include", "hamming.h")).read()
+    assert re.search(r"#define HAMMING_NOALLOC_MAX_PACKETS 65536u", text)
+    assert re.search(r"#define HAMMING_NOALLOC_SCRATCH_BYTES \(4u << 20\)", text)
+    assert hm.HAMMING_NOALLOC_MAX_PACKETS == 65536 and hm.HAMMING_NOALLOC_SCRATCH_BYTES == 4 << 20
+    assert hm.hamming_batch_workspace_min_bytes(hm.HAMMING_NOALLOC_MAX_PACKETS) <= hm.HAMMING_NOALLOC_SCRATCH_BYTES
+    lib = hm.library()
+    A = 1 << 20
+    call = lambda maxp: lib.hamming_decode_batch_noalloc(A, 100, A, A, maxp, 0, A, 100, A, 100, A, 0)
+    # both return before any HIP call
+    assert call(0) == hm.HAMMING_OK
+    assert call(hm.HAMMING_NOALLOC_MAX_PACKETS + 1) == hm.HAMMING_ERANGE
+    assert call(hm.HAMMING_MAX_BATCH + 1) == hm.HAMMING_ERANGE
+
+
 def test_batch_workspace_sizes():
     # header (64 bytes) + tile prefix sums (8 per packet + 1) + coarse map (4 * (2n + 1024)) before the fine map
     for n in (0, 1, 10, 1000, 1 << 20):
