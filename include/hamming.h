@@ -242,11 +242,23 @@ int hamming_decode_batch(const uint64_t *cw_arena, uint64_t cw_words,
 int hamming_batch_config_set(int schedule, uint32_t xcd_chunk, uint32_t grid_cap_blocks, int use_graph);
 int hamming_batch_config_get(int *schedule, uint32_t *xcd_chunk, uint32_t *grid_cap_blocks, int *use_graph);
 
+/*
+ * Work unit of the batched decode kernels (a tuning knob, no effect on
+ * results): a wave takes 2^tiles_log2 consecutive tiles of the batch's tile
+ * order, finds the packet of the first once and decodes each packet's share
+ * with the next tile's loads in flight (tiles_log2 in [0, 6], default 3).
+ * The one-launch form for at most 16 served requests keeps one tile per
+ * wave.  Process-wide; set before decoding (cached hipGraphs are keyed on
+ * it).  Returns HAMMING_OK or HAMMING_EINVAL.
+ */
+int hamming_batch_chunk_set(uint32_t tiles_log2);
+int hamming_batch_chunk_get(uint32_t *tiles_log2);
+
 /* Workgroups of the batched decode kernel for these arguments of
- * hamming_decode_batch: one wave per tile of the largest batch they allow
- * (min(cw_words/256, max_codewords/128) + max_packets tiles; max_codewords 0 =
- * no hint), capped by grid_cap_blocks and by the 2^32-1 work-items a dispatch
- * can hold.  Host-only and informative; 0 if max_packets is 0 or above
+ * hamming_decode_batch: one wave per chunk (hamming_batch_chunk_set) of the
+ * largest batch they allow (min(cw_words/256, max_codewords/128) +
+ * max_packets tiles; max_codewords 0 = no hint), capped by grid_cap_blocks
+ * and by the 2^32-1 work-items a dispatch can hold.  Host-only and informative; 0 if max_packets is 0 or above
  * HAMMING_MAX_BATCH. */
 uint64_t hamming_decode_batch_grid(uint64_t cw_words, uint32_t max_packets, uint64_t max_codewords);
 
@@ -458,12 +470,13 @@ int hamming_decode_host(const uint64_t *host_cw, uint64_t n_cw, int r, void *hos
 
 /*
  * Autotuner: on the current device and `stream`, time the plain decode of
- * random 2^26-codeword packets (2^25 for r = 7) for every lane width and XCD
- * chunking, and the batched decode of a batch of up to 2,000 packets (sizes
- * log-uniform in [64, 2^20] codewords, r uniform in 3..7, packed into a
- * 2^28-word (2 GiB) codeword arena) for every schedule and XCD chunking;
- * apply the fastest shapes (as hamming_plain_config_set /
- * hamming_batch_config_set would) and, when cache_path is neither NULL nor
+ * random 2^26-codeword packets (2^25 for r = 7) for every lane width, grid
+ * cap and XCD chunking, and the batched decode of a batch of up to 2,000
+ * packets (sizes log-uniform in [64, 2^20] codewords, r uniform in 3..7,
+ * packed into a 2^28-word (2 GiB) codeword arena) for every schedule, XCD
+ * chunking and work chunk; apply the fastest shapes (as
+ * hamming_plain_config_set / hamming_batch_config_set /
+ * hamming_batch_chunk_set would) and, when cache_path is neither NULL nor
  * empty, write them there.  flags: bit 0 tunes the plain decode, bit 1 the
  * batched decode.  Allocates up to about 5 GB of device memory for the
  * duration of the call (1.1 GB for the plain trials, the batch arena and its

@@ -57,6 +57,8 @@ _SIGNATURES = {
                               _vp], _i32),
     "hamming_decode_batch_noalloc": ([_vp, _u64, _vp, _vp, ctypes.c_uint32, _u64, _vp, _u64, _vp, _u64, _vp,
                                       _vp], _i32),
+    "hamming_batch_chunk_set": ([ctypes.c_uint32], _i32),
+    "hamming_batch_chunk_get": ([ctypes.POINTER(ctypes.c_uint32)], _i32),
     "hamming_batch_config_set": ([_i32, ctypes.c_uint32, ctypes.c_uint32, _i32], _i32),
     "hamming_batch_config_get": ([ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_uint32),
                                   ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_i32)], _i32),
@@ -275,6 +277,16 @@ def hamming_decode_batch_noalloc(cw_arena, cw_words: int, descs, n_packets_dev, 
 
 HAMMING_NOALLOC_MAX_PACKETS = 65536
 HAMMING_NOALLOC_SCRATCH_BYTES = 4 << 20
+
+
+def hamming_batch_chunk_set(tiles_log2: int) -> None:
+    _check(library().hamming_batch_chunk_set(tiles_log2), "hamming_batch_chunk_set")
+
+
+def hamming_batch_chunk_get() -> int:
+    v = ctypes.c_uint32()
+    _check(library().hamming_batch_chunk_get(ctypes.byref(v)), "hamming_batch_chunk_get")
+    return v.value
 
 
 def hamming_batch_config_set(schedule: int, xcd_chunk: int = 1, grid_cap_blocks: int = 0,

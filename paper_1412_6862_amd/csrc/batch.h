@@ -13,7 +13,7 @@ namespace hm {
 // Head of the caller's workspace.  After it: tile_start[max_packets + 1]
 // (uint64, exclusive prefix sum of tiles per packet), coarse[coarse_cap] and
 // fine[fine_cap] (uint32): coarse[j] is the packet holding tile j << coarse_log2,
-// fine[j] the packet holding tile j << fine_log2.
+// fine[j] the packet holding tile j << fine_log2 (fine_log2 >= chunk_log2).
 struct BatchWs {
     uint64_t total_tiles;   // tiles of the whole batch
     uint64_t n_packets;     // packets planned (clamped to max_packets)
@@ -43,6 +43,7 @@ struct BatchArgs {
     uint32_t coarse_cap;
     uint32_t fine_cap;
     uint32_t fine_blocks;   // grid of the fine-map kernel (it loops over entries beyond the grid)
+    uint32_t chunk_log2;    // a wave's unit of work: 2^chunk_log2 consecutive tiles
 };
 
 constexpr uint32_t batch_coarse_capacity(uint32_t max_packets) { return 2 * max_packets + 1024; }
@@ -99,8 +100,13 @@ int batch_prepare(const uint64_t* cw_arena, uint64_t cw_words, const hamming_pac
                   uint64_t data_words, uint8_t* errpos_arena, uint64_t errpos_bytes, int32_t* status_out,
                   void* workspace, uint64_t workspace_bytes, BatchArgs* out, uint32_t* grid);
 
-// The batch schedule in force (hamming_batch_config_set).
+// The batch schedule in force (hamming_batch_config_set) and the chunk size
+// (hamming_batch_chunk_set).
 int batch_schedule();
+uint32_t batch_chunk_log2();
+
+// Largest chunk: 2^6 tiles.
+constexpr uint32_t kMaxChunkLog2 = 6;
 
 // A batch small enough to travel in the kernel arguments: its descriptors
 // and the exclusive prefix sum of their tile counts, computed on the host by
@@ -136,7 +142,7 @@ struct PlannedBatch {
     uint32_t n;
     uint32_t coarse_log2;
     uint32_t xcd_chunk;
-    uint32_t reserved;
+    uint32_t chunk_log2;            // a wave's unit of work: 2^chunk_log2 consecutive tiles
 };
 
 // Bytes of a host plan of n packets: prefix sums, coarse map (padded to 8

@@ -20,6 +20,7 @@ std::atomic<int> g_schedule{3};
 std::atomic<uint32_t> g_grid_cap{0};
 std::atomic<uint32_t> g_xcd_chunk{1};
 std::atomic<int> g_use_graph{1};
+std::atomic<uint32_t> g_chunk_log2{3};
 
 struct GraphKey {
     BatchArgs a;
@@ -117,14 +118,16 @@ uint64_t batch_tile_bound(uint64_t cw_words, uint32_t max_packets, uint64_t max_
     return tiles + uint64_t(max_packets);
 }
 
-// Workgroups of the batched decode kernel: one wave per tile of the bound
-// (waves beyond the real tile count only read the totals and exit, but at 4x
-// the tile count they cost a visible tail), capped by the configured cap and
-// by the dispatch limit, beyond which waves loop over tiles.
-uint64_t batch_grid_blocks(uint64_t cw_words, uint32_t max_packets, uint64_t max_codewords, uint64_t cap)
+// Workgroups of the batched decode kernel: one wave per chunk of the tile
+// bound (waves beyond the real chunk count only read the totals and exit,
+// but at 4x the count they cost a visible tail), capped by the configured cap
+// and by the dispatch limit, beyond which waves loop over chunks.
+uint64_t batch_grid_blocks(uint64_t cw_words, uint32_t max_packets, uint64_t max_codewords, uint64_t cap,
+                           uint32_t chunk_log2)
 {
-    uint64_t blocks = (batch_tile_bound(cw_words, max_packets, max_codewords) + hm::kWavesPerBlockHost - 1) /
-                      hm::kWavesPerBlockHost;
+    const uint64_t chunks = (batch_tile_bound(cw_words, max_packets, max_codewords) + (uint64_t(1) << chunk_log2) - 1) >>
+                            chunk_log2;
+    uint64_t blocks = (chunks + hm::kWavesPerBlockHost - 1) / hm::kWavesPerBlockHost;
     if (cap && blocks > cap) blocks = cap;
     if (blocks > hm::max_launch_blocks(256)) blocks = hm::max_launch_blocks(256);
     if (blocks < 1) blocks = 1;
@@ -161,6 +164,7 @@ int batch_prepare(const uint64_t* cw_arena, uint64_t cw_words, const hamming_pac
     a.errpos_bytes = errpos_arena ? errpos_bytes : 0;
     a.status_out = status_out;
     a.xcd_chunk = g_xcd_chunk.load();
+    a.chunk_log2 = g_chunk_log2.load();
     a.coarse_cap = hm::batch_coarse_capacity(max_packets);
     a.fine_cap = hm::batch_fine_capacity(max_packets, workspace_bytes);
     a.ws = static_cast<hm::BatchWs*>(workspace);
@@ -168,17 +172,19 @@ int batch_prepare(const uint64_t* cw_arena, uint64_t cw_words, const hamming_pac
     a.coarse = reinterpret_cast<uint32_t*>(a.tile_start + (uint64_t(max_packets) + 1));
     a.fine = a.coarse + a.coarse_cap;
 
-    const uint64_t blocks = batch_grid_blocks(cw_words, max_packets, max_codewords, g_grid_cap.load());
+    const uint64_t blocks = batch_grid_blocks(cw_words, max_packets, max_codewords, g_grid_cap.load(), a.chunk_log2);
     *grid = uint32_t(blocks);
-    // the fine map has at most one entry per tile of the bound (its kernel is
-    // grid-stride, so this only sizes its grid)
-    const uint64_t tiles = batch_tile_bound(cw_words, max_packets, max_codewords);
-    const uint64_t fine_entries = tiles < a.fine_cap ? tiles : a.fine_cap;
+    // the fine map has at most one entry per chunk of the bound (its kernel
+    // is grid-stride, so this only sizes its grid)
+    const uint64_t chunks = (batch_tile_bound(cw_words, max_packets, max_codewords) + (uint64_t(1) << a.chunk_log2) - 1) >>
+                            a.chunk_log2;
+    const uint64_t fine_entries = chunks < a.fine_cap ? chunks : a.fine_cap;
     a.fine_blocks = uint32_t((fine_entries + 255) / 256);
     return HAMMING_OK;
 }
 
 int batch_schedule() { return g_schedule.load(); }
+uint32_t batch_chunk_log2() { return g_chunk_log2.load(); }
 
 }  // namespace hm
 
@@ -227,6 +233,20 @@ int hamming_batch_config_set(int schedule, uint32_t xcd_chunk, uint32_t grid_cap
     g_xcd_chunk.store(xcd_chunk);
     g_grid_cap.store(grid_cap_blocks);
     g_use_graph.store(use_graph);
+    return HAMMING_OK;
+}
+
+int hamming_batch_chunk_set(uint32_t tiles_log2)
+{
+    if (tiles_log2 > hm::kMaxChunkLog2) return HAMMING_EINVAL;
+    g_chunk_log2.store(tiles_log2);
+    return HAMMING_OK;
+}
+
+int hamming_batch_chunk_get(uint32_t* tiles_log2)
+{
+    if (!tiles_log2) return HAMMING_EINVAL;
+    *tiles_log2 = g_chunk_log2.load();
     return HAMMING_OK;
 }
 
@@ -314,7 +334,7 @@ int hamming_batch_release_graphs(void)
 uint64_t hamming_decode_batch_grid(uint64_t cw_words, uint32_t max_packets, uint64_t max_codewords)
 {
     if (max_packets == 0 || max_packets > HAMMING_MAX_BATCH) return 0;
-    return batch_grid_blocks(cw_words, max_packets, max_codewords, g_grid_cap.load());
+    return batch_grid_blocks(cw_words, max_packets, max_codewords, g_grid_cap.load(), g_chunk_log2.load());
 }
 
 }  // extern "C"

@@ -1,23 +1,28 @@
 // Batched decode: many packets of mixed size and r in one launch sequence.
 //
 // The arithmetic is the plain decode's (tile.h); only the work distribution
-// differs.  Four kernels, all replayable from a hipGraph with no host work:
+// differs.  Tiles are 64*U codewords aligned to their packet's start, and the
+// batch's tiles are numbered in packet order.  Work is dealt in chunks of
+// 2^c consecutive tiles: a wave finds the packet of its chunk's first tile
+// once, then decodes the chunk packet by packet, each packet's share as one
+// pipelined run (the next tile's loads in flight while the current one is
+// decoded), so the lookup and its dependent loads are paid per chunk rather
+// than per tile.  Chunks go to waves in order, as the hardware dispatches the
+// plain grid, so the chunks in flight form one advancing window of memory.
+// Four kernels, all replayable from a hipGraph with no host work:
 //  * batch_plan_kernel (one workgroup) validates every descriptor, writes its
-//    status and an exclusive prefix sum of its tile count (tiles are 64*U
-//    codewords aligned to the packet's start), and picks the group sizes of
-//    two tile-to-packet maps so that each fits its capacity;
+//    status and an exclusive prefix sum of its tile count, and picks the
+//    group sizes of two chunk-to-packet maps so that each fits its capacity;
 //  * batch_coarse_kernel fills the coarse map by binary search over the
 //    prefix sums; batch_fine_kernel fills the fine map (normally one entry
-//    per tile) by a short binary search between two coarse entries;
-//  * decode_batch_kernel gives one tile to each wave in global tile order, as
-//    the hardware dispatches the plain grid, so the tiles in flight form one
-//    advancing window of memory.  A wave reads its packet from the fine map
-//    (plus a 64-lane probe when a fine entry spans several tiles), then
-//    decodes the tile exactly as the plain kernel would.  A grid smaller than
-//    the batch loops.
+//    per chunk) by a short binary search between two coarse entries;
+//  * decode_batch_kernel reads a chunk's packet from the fine map (plus a
+//    64-lane probe when a fine entry spans several chunks) and decodes it.  A
+//    grid smaller than the batch loops.
 // A batch of at most kSmallBatchMax packets validated by its caller can
 // instead carry its descriptors and tile prefix sums in the kernel arguments
-// of decode_small_batch_kernel: one launch, no copy and no maps.
+// of decode_small_batch_kernel: one launch, no copy and no maps, one tile
+// per wave (the latency form).
 // Each packet's output is the same words a plain call would write.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -46,9 +51,9 @@ struct Schedule {
 };
 
 using Sched0 = Schedule<8, 8, 8, 8, 2, 4>;
-using Sched1 = Schedule<8, 4, 4, 4, 2, 6>;
-using Sched2 = Schedule<8, 4, 4, 4, 2, 8>;
-using Sched3 = Schedule<8, 8, 8, 4, 2, 8>;
+using Sched1 = Schedule<8, 4, 4, 4, 2, 5>;
+using Sched2 = Schedule<8, 8, 8, 4, 2, 5>;
+using Sched3 = Schedule<8, 8, 8, 8, 4, 4>;
 
 __device__ __forceinline__ uint64_t message_words(uint64_t n_cw, uint32_t r)
 {
@@ -124,8 +129,10 @@ __global__ __launch_bounds__(1024) void batch_plan_kernel(BatchArgs a)
         __syncthreads();
     }
     if (tid == 0) {
-        uint32_t gc = 0, gf = 0;
-        while ((carry >> gc) >= a.coarse_cap) ++gc;      // entries = ceil(total / 2^g) <= capacity
+        // entries = ceil(total / 2^g) <= capacity; the fine map needs at most
+        // one entry per chunk (lookups are made at chunk starts only)
+        uint32_t gc = 0, gf = a.chunk_log2;
+        while ((carry >> gc) >= a.coarse_cap) ++gc;
         while ((carry >> gf) >= a.fine_cap) ++gf;
         a.tile_start[n] = carry;
         a.ws->total_tiles = carry;
@@ -184,30 +191,51 @@ __device__ __forceinline__ uint32_t probe_packet(const uint64_t* ts, uint32_t n,
     }
 }
 
+// Tiles [tl0, tl1) of one packet as one pipelined run.
 template <int R, int U>
-__device__ __forceinline__ void decode_packet_tile(const hamming_packet& d, uint64_t tl, const uint64_t* cw_arena,
-                                                   uint64_t* data_arena, uint8_t* errpos_arena, uint32_t* lds)
+__device__ __forceinline__ void decode_packet_run(const hamming_packet& d, uint64_t tl0, uint64_t tl1,
+                                                  const uint64_t* cw_arena, uint64_t* data_arena,
+                                                  uint8_t* errpos_arena, uint32_t* lds)
 {
     const uint64_t* cw = cw_arena + d.in_word_off;
     uint64_t* data = data_arena + d.data_word_off;
     uint8_t* ep = (d.errpos_off == HAMMING_NO_ERRPOS) ? nullptr : errpos_arena + d.errpos_off;
-    uint32_t flags = 0;
-    if ((reinterpret_cast<uintptr_t>(cw) & 15u) == 0) flags |= kFlagIn16;
-    if (ep && (reinterpret_cast<uintptr_t>(ep) % U) == 0) flags |= kFlagEpVec;
-    if ((reinterpret_cast<uintptr_t>(data) & 15u) == 0) flags |= kFlagOut16;
-    decode_tile<R, U>(cw, d.n_cw, tl, data, message_words(d.n_cw, R), ep, lds, flags);
+    const uint32_t flags = (ep && (reinterpret_cast<uintptr_t>(ep) % U) == 0) ? kFlagEpVec : 0u;
+    decode_run<R, U>(cw, d.n_cw, tl0, tl1, 1, data, message_words(d.n_cw, R), ep, lds, flags);
 }
 
 template <class S>
-__device__ __forceinline__ void decode_any_tile(const hamming_packet& d, uint64_t tl, const uint64_t* cw_arena,
-                                                uint64_t* data_arena, uint8_t* errpos_arena, uint32_t* lds)
+__device__ __forceinline__ void decode_any_run(const hamming_packet& d, uint64_t tl0, uint64_t tl1,
+                                               const uint64_t* cw_arena, uint64_t* data_arena,
+                                               uint8_t* errpos_arena, uint32_t* lds)
 {
     switch (d.r) {
-    case 3: decode_packet_tile<3, S::u[0]>(d, tl, cw_arena, data_arena, errpos_arena, lds); break;
-    case 4: decode_packet_tile<4, S::u[1]>(d, tl, cw_arena, data_arena, errpos_arena, lds); break;
-    case 5: decode_packet_tile<5, S::u[2]>(d, tl, cw_arena, data_arena, errpos_arena, lds); break;
-    case 6: decode_packet_tile<6, S::u[3]>(d, tl, cw_arena, data_arena, errpos_arena, lds); break;
-    default: decode_packet_tile<7, S::u[4]>(d, tl, cw_arena, data_arena, errpos_arena, lds); break;
+    case 3: decode_packet_run<3, S::u[0]>(d, tl0, tl1, cw_arena, data_arena, errpos_arena, lds); break;
+    case 4: decode_packet_run<4, S::u[1]>(d, tl0, tl1, cw_arena, data_arena, errpos_arena, lds); break;
+    case 5: decode_packet_run<5, S::u[2]>(d, tl0, tl1, cw_arena, data_arena, errpos_arena, lds); break;
+    case 6: decode_packet_run<6, S::u[3]>(d, tl0, tl1, cw_arena, data_arena, errpos_arena, lds); break;
+    default: decode_packet_run<7, S::u[4]>(d, tl0, tl1, cw_arena, data_arena, errpos_arena, lds); break;
+    }
+}
+
+// Tiles [t, t_end) of the batch in tile order, p being the packet that holds
+// tile t (ts[p] <= t < ts[p + 1]): one run per packet, packets without tiles
+// passed over.  All values are uniform across the wave.
+template <class S>
+__device__ __forceinline__ void decode_span(uint64_t t, uint64_t t_end, uint32_t p, const uint64_t* ts,
+                                            const hamming_packet* descs, const uint64_t* cw_arena,
+                                            uint64_t* data_arena, uint8_t* errpos_arena, uint32_t* lds)
+{
+    while (t < t_end) {
+        const uint64_t t1 = ts[p + 1];
+        if (t1 > t) {
+            const hamming_packet d = descs[p];
+            const uint64_t t0 = ts[p];
+            const uint64_t e = t1 < t_end ? t1 : t_end;
+            decode_any_run<S>(d, t - t0, e - t0, cw_arena, data_arena, errpos_arena, lds);
+            t = e;
+        }
+        ++p;
     }
 }
 
@@ -218,29 +246,30 @@ void decode_batch_kernel(
     const uint64_t* __restrict__ ts, const hamming_packet* __restrict__ descs)
 {
     __shared__ u32x4 lds_raw[kWavesPerBlock][S::LDS_MAX / 4];
-    // the wave index is uniform: keep tile bookkeeping in scalar registers so
+    // the wave index is uniform: keep chunk bookkeeping in scalar registers so
     // the table and descriptor reads below are scalar loads
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t* lds = reinterpret_cast<uint32_t*>(&lds_raw[wave][0]);
     const uint64_t waves = uint64_t(gridDim.x) * kWavesPerBlock;
-    uint64_t t = uint64_t(xcd_block(blockIdx.x, gridDim.x, a.xcd_chunk)) * kWavesPerBlock + wave;
-    // Read this tile's map entry together with the batch totals instead of
-    // after them: when the map has one entry per tile (fine_log2 = 0, the
-    // usual case) it is the entry needed.  The index is clamped to the map, so
-    // the read stays in bounds whatever the totals turn out to be.
-    const uint32_t p_first = fine[t < a.fine_cap ? t : a.fine_cap - 1];
+    const uint32_t cl = a.chunk_log2;
+    uint64_t c = uint64_t(xcd_block(blockIdx.x, gridDim.x, a.xcd_chunk)) * kWavesPerBlock + wave;
+    // Read this chunk's map entry together with the batch totals instead of
+    // after them: when the map has one entry per chunk (fine_log2 = chunk
+    // log2, the usual case) it is the entry needed.  The index is clamped to
+    // the map, so the read stays in bounds whatever the totals turn out to be.
+    const uint32_t p_first = fine[c < a.fine_cap ? c : a.fine_cap - 1];
     const uint64_t total = ws->total_tiles;
-    if (t >= total) return;
+    if ((c << cl) >= total) return;
     const uint32_t n = uint32_t(ws->n_packets);
-    const uint32_t gf = ws->fine_log2;
+    const uint32_t gf = ws->fine_log2;            // >= cl
     bool first = true;
-    for (; t < total; t += waves) {
-        uint32_t p = (first && gf == 0) ? p_first : fine[t >> gf];
+    for (; (c << cl) < total; c += waves) {
+        const uint64_t t = c << cl;
+        uint32_t p = (first && gf == cl) ? p_first : fine[t >> gf];
         first = false;
-        if (gf) p = probe_packet(ts, n, t, p);
-        const hamming_packet d = descs[p];
-        const uint64_t tl = t - ts[p];
-        decode_any_tile<S>(d, tl, a.cw_arena, a.data_arena, a.errpos_arena, lds);
+        if (gf > cl) p = probe_packet(ts, n, t, p);
+        const uint64_t t_end = (t + (uint64_t(1) << cl) < total) ? t + (uint64_t(1) << cl) : total;
+        decode_span<S>(t, t_end, p, ts, descs, a.cw_arena, a.data_arena, a.errpos_arena, lds);
     }
 }
 
@@ -259,12 +288,14 @@ void decode_small_batch_kernel(SmallBatch b)
     uint32_t p = 0;
     while (p + 1 < b.n && b.tile_start[p + 1] <= t) ++p;    // packets without tiles are passed over
     const hamming_packet d = b.descs[p];
-    decode_any_tile<S>(d, t - b.tile_start[p], b.cw_arena, b.data_arena, b.errpos_arena, lds);
+    decode_any_run<S>(d, t - b.tile_start[p], t + 1 - b.tile_start[p], b.cw_arena, b.data_arena, b.errpos_arena,
+                      lds);
 }
 
-// The host-planned form: one tile per wave in global tile order (waves loop
-// when the batch has more tiles than a dispatch can hold), the packet found
-// from the coarse map entry by a 64-lane probe of the prefix sums.
+// The host-planned form: chunks of 2^c tiles in order (waves loop when the
+// batch has more chunks than a dispatch can hold), the packet of a chunk's
+// first tile found from the coarse map entry by a 64-lane probe of the prefix
+// sums.
 template <class S>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(S::waves_per_simd)))
 void decode_planned_batch_kernel(PlannedBatch b)
@@ -273,18 +304,21 @@ void decode_planned_batch_kernel(PlannedBatch b)
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t* lds = reinterpret_cast<uint32_t*>(&lds_raw[wave][0]);
     const uint64_t waves = uint64_t(gridDim.x) * kWavesPerBlock;
-    for (uint64_t t = uint64_t(xcd_block(blockIdx.x, gridDim.x, b.xcd_chunk)) * kWavesPerBlock + wave;
-         t < b.total_tiles; t += waves) {
+    const uint32_t cl = b.chunk_log2;
+    for (uint64_t c = uint64_t(xcd_block(blockIdx.x, gridDim.x, b.xcd_chunk)) * kWavesPerBlock + wave;
+         (c << cl) < b.total_tiles; c += waves) {
+        const uint64_t t = c << cl;
         const uint32_t p = probe_packet(b.tile_start, b.n, t, b.coarse[t >> b.coarse_log2]);
-        const hamming_packet d = b.descs[p];
-        decode_any_tile<S>(d, t - b.tile_start[p], b.cw_arena, b.data_arena, b.errpos_arena, lds);
+        const uint64_t t_end = (t + (uint64_t(1) << cl) < b.total_tiles) ? t + (uint64_t(1) << cl) : b.total_tiles;
+        decode_span<S>(t, t_end, p, b.tile_start, b.descs, b.cw_arena, b.data_arena, b.errpos_arena, lds);
     }
 }
 
 template <class S>
 static hipError_t launch_planned_s(const PlannedBatch& b, hipStream_t stream)
 {
-    uint64_t blocks = (b.total_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    const uint64_t chunks = (b.total_tiles + (uint64_t(1) << b.chunk_log2) - 1) >> b.chunk_log2;
+    uint64_t blocks = (chunks + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks > max_launch_blocks(kBlockThreads)) blocks = max_launch_blocks(kBlockThreads);
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL((decode_planned_batch_kernel<S>), dim3(uint32_t(blocks)), dim3(kBlockThreads), 0, stream, b);

@@ -212,6 +212,7 @@ int launch_planned(hamming_server* s, Slot& sl, uint32_t n, int schedule, uint32
     b.n = n;
     b.coarse_log2 = g;
     b.xcd_chunk = xcd_chunk;
+    b.chunk_log2 = hm::batch_chunk_log2();
     return hm::launch_planned_batch(b, schedule, sl.stream) == hipSuccess ? HAMMING_OK : HAMMING_EDEVICE;
 }
 

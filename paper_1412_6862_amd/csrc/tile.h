@@ -26,6 +26,10 @@
 namespace hm {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// The same 16-byte vector at 8-byte alignment: packets and message streams
+// start at any 64-bit word, and a global dwordx4 access needs only dword
+// alignment, so every full tile takes the vector path.
+typedef uint32_t u32x4a8 __attribute__((ext_vector_type(4), aligned(8)));
 
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlockThreads = 64 * kWavesPerBlock;
@@ -126,15 +130,14 @@ struct TileIn {
 // Issue the loads of tile `tile` (codewords past n_cw read as zero).
 template <int R, int U>
 __device__ __forceinline__ void load_tile(const uint64_t* __restrict__ cw, uint64_t n_cw, uint64_t tile,
-                                          uint32_t flags, TileIn<R, U>& t)
+                                          uint32_t lane, TileIn<R, U>& t)
 {
     using C = Code<R>;
     using T = TileShape<R, U>;
-    const uint32_t lane = threadIdx.x & 63u;
     const bool full = (tile + 1) * T::CW <= n_cw;
-    t.coalesced = full && (flags & kFlagIn16);
+    t.coalesced = full;
     if (t.coalesced) {
-        const u32x4* src = reinterpret_cast<const u32x4*>(cw + tile * T::CW * C::WPC) + lane;
+        const u32x4a8* src = reinterpret_cast<const u32x4a8*>(cw + tile * T::CW * C::WPC) + lane;
 #pragma unroll
         for (int v = 0; v < T::NV; ++v) {
             const u32x4 x = __builtin_nontemporal_load(src + 64 * v);
@@ -157,16 +160,16 @@ __device__ __forceinline__ void load_tile(const uint64_t* __restrict__ cw, uint6
     }
 }
 
-// Issue the loads of a tile known to be full, from a 16-byte aligned packet
-// (the vector form of load_tile with no checks).
+// Issue the loads of a tile known to be full (the vector form of load_tile
+// with no checks).
 template <int R, int U>
-__device__ __forceinline__ void load_full_tile(const uint64_t* __restrict__ cw, uint64_t tile, TileIn<R, U>& t)
+__device__ __forceinline__ void load_full_tile(const uint64_t* __restrict__ cw, uint64_t tile, uint32_t lane,
+                                               TileIn<R, U>& t)
 {
     using C = Code<R>;
     using T = TileShape<R, U>;
-    const uint32_t lane = threadIdx.x & 63u;
     t.coalesced = true;
-    const u32x4* src = reinterpret_cast<const u32x4*>(cw + tile * T::CW * C::WPC) + lane;
+    const u32x4a8* src = reinterpret_cast<const u32x4a8*>(cw + tile * T::CW * C::WPC) + lane;
 #pragma unroll
     for (int v = 0; v < T::NV; ++v) {
         const u32x4 x = __builtin_nontemporal_load(src + 64 * v);
@@ -179,12 +182,11 @@ __device__ __forceinline__ void load_full_tile(const uint64_t* __restrict__ cw, 
 
 // Decode the loaded codewords of tile `tile` and write its outputs.
 template <int R, int U>
-__device__ __forceinline__ void finish_tile(TileIn<R, U>& tin, uint64_t n_cw, uint64_t tile,
+__device__ __forceinline__ void finish_tile(TileIn<R, U>& tin, uint64_t n_cw, uint64_t tile, uint32_t lane,
                                             uint64_t* __restrict__ data, uint64_t data_words,
                                             uint8_t* __restrict__ errpos, uint32_t* lds, uint32_t flags)
 {
     using T = TileShape<R, U>;
-    const uint32_t lane = threadIdx.x & 63u;
     const uint64_t c0 = tile * T::CW + uint64_t(lane) * U;
     const bool full = (tile + 1) * T::CW <= n_cw;
     auto& in = tin.in;
@@ -275,10 +277,10 @@ __device__ __forceinline__ void finish_tile(TileIn<R, U>& tin, uint64_t n_cw, ui
 
     // ---- LDS -> global by consecutive lanes ---------------------------------
     const uint64_t w0 = tile * uint64_t(T::WORDS);
-    if (full && (flags & kFlagOut16)) {
-        // whole tile, 16-byte aligned: T::WORDS is even (U is even)
+    if (full) {
+        // whole tile: T::WORDS is even (U is even)
         const u32x4* l4 = reinterpret_cast<const u32x4*>(lds);
-        u32x4* dst = reinterpret_cast<u32x4*>(data + w0);
+        u32x4a8* dst = reinterpret_cast<u32x4a8*>(data + w0);
 #pragma unroll
         for (int q = 0; q < (T::WORDS / 2 + 63) / 64; ++q) {
             const uint32_t j = lane + 64u * q;
@@ -301,12 +303,56 @@ __device__ __forceinline__ void finish_tile(TileIn<R, U>& tin, uint64_t n_cw, ui
 
 template <int R, int U>
 __device__ __forceinline__ void decode_tile(const uint64_t* __restrict__ cw, uint64_t n_cw, uint64_t tile,
-                                            uint64_t* __restrict__ data, uint64_t data_words,
+                                            uint32_t lane, uint64_t* __restrict__ data, uint64_t data_words,
                                             uint8_t* __restrict__ errpos, uint32_t* lds, uint32_t flags)
 {
     TileIn<R, U> t;
-    load_tile<R, U>(cw, n_cw, tile, flags, t);
-    finish_tile<R, U>(t, n_cw, tile, data, data_words, errpos, lds, flags);
+    load_tile<R, U>(cw, n_cw, tile, lane, t);
+    finish_tile<R, U>(t, n_cw, tile, lane, data, data_words, errpos, lds, flags);
+}
+
+// Lane index within the wave, made opaque to the optimiser: lane-derived
+// addresses are then computed where a run starts instead of being hoisted
+// out of the loops around it (a batch kernel holds a run for every r, and
+// values hoisted for all of them at once would exceed its register budget).
+__device__ __forceinline__ uint32_t run_lane()
+{
+    uint32_t l = threadIdx.x & 63u;
+    asm volatile("" : "+v"(l));
+    return l;
+}
+
+// Tiles t, t + stride, ... below t_end of one packet.  The full ones run as a
+// two-stage pipeline: the wave issues the loads of its next full tile before
+// it decodes the current one, so two tiles of loads are in flight while it
+// computes.  Tiles past the last full one (at most the ragged tile) go
+// through the checked path.
+template <int R, int U>
+__device__ __forceinline__ void decode_run(const uint64_t* __restrict__ cw, uint64_t n_cw, uint64_t t,
+                                           uint64_t t_end, uint64_t stride, uint64_t* __restrict__ data,
+                                           uint64_t data_words, uint8_t* __restrict__ errpos, uint32_t* lds,
+                                           uint32_t flags)
+{
+    using T = TileShape<R, U>;
+    const uint32_t lane = run_lane();
+    const uint64_t n_full = n_cw / T::CW;
+    const uint64_t full_end = t_end < n_full ? t_end : n_full;
+    if (t < full_end) {
+        TileIn<R, U> cur;
+        load_full_tile<R, U>(cw, t, lane, cur);
+        for (;;) {
+            const uint64_t tn = t + stride;
+            if (tn >= full_end) break;
+            TileIn<R, U> nxt;
+            load_full_tile<R, U>(cw, tn, lane, nxt);    // in flight while `cur` is decoded
+            finish_tile<R, U>(cur, n_cw, t, lane, data, data_words, errpos, lds, flags);
+            cur = nxt;
+            t = tn;
+        }
+        finish_tile<R, U>(cur, n_cw, t, lane, data, data_words, errpos, lds, flags);
+        t += stride;
+    }
+    for (; t < t_end; t += stride) decode_tile<R, U>(cw, n_cw, t, lane, data, data_words, errpos, lds, flags);
 }
 
 }  // namespace hm

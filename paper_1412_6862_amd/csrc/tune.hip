@@ -63,6 +63,7 @@ struct BatchChoice {
     int schedule;
     uint32_t xcd_chunk, grid_cap;
     int use_graph;
+    uint32_t chunk_log2;
     float ms;
 };
 
@@ -141,6 +142,7 @@ int hamming_tune(const char* cache_path, uint32_t flags, hipStream_t stream)
     {
         uint32_t xc0, cap0;
         hamming_batch_config_get(&batch.schedule, &xc0, &cap0, &batch.use_graph);
+        hamming_batch_chunk_get(&batch.chunk_log2);
         batch.xcd_chunk = xc0;
         batch.grid_cap = cap0;
         batch.ms = 0;
@@ -197,22 +199,27 @@ int hamming_tune(const char* cache_path, uint32_t flags, hipStream_t stream)
         float best = 1e30f;
         for (int sched : {0, 1, 2, 3}) {
             for (uint32_t xc : kXcdChoices) {
-                // direct launches while tuning: no graph is cached for these scratch buffers
-                if (hamming_batch_config_set(sched, xc, 0, 0) != HAMMING_OK) return HAMMING_EINVAL;
-                float ms = 0;
-                rc = time_ms(stream, 2, 5, [&] {
-                    return hamming_decode_batch(static_cast<const uint64_t*>(bcw.p), off, dd, n_dev, nb, total,
-                                                static_cast<uint64_t*>(bdata.p), dw, static_cast<uint8_t*>(bep.p), eb,
-                                                nullptr, ws.p, wsb, stream);
-                }, &ms);
-                if (rc != HAMMING_OK) return rc;
-                if (ms < best) {
-                    best = ms;
-                    batch = {sched, xc, 0, 1, ms};
+                for (uint32_t cl : {0u, 2u, 3u, 4u, 5u}) {
+                    // direct launches while tuning: no graph is cached for these scratch buffers
+                    if (hamming_batch_config_set(sched, xc, 0, 0) != HAMMING_OK ||
+                        hamming_batch_chunk_set(cl) != HAMMING_OK)
+                        return HAMMING_EINVAL;
+                    float ms = 0;
+                    rc = time_ms(stream, 2, 5, [&] {
+                        return hamming_decode_batch(static_cast<const uint64_t*>(bcw.p), off, dd, n_dev, nb, total,
+                                                    static_cast<uint64_t*>(bdata.p), dw, static_cast<uint8_t*>(bep.p),
+                                                    eb, nullptr, ws.p, wsb, stream);
+                    }, &ms);
+                    if (rc != HAMMING_OK) return rc;
+                    if (ms < best) {
+                        best = ms;
+                        batch = {sched, xc, 0, 1, cl, ms};
+                    }
                 }
             }
         }
         hamming_batch_config_set(batch.schedule, batch.xcd_chunk, batch.grid_cap, batch.use_graph);
+        hamming_batch_chunk_set(batch.chunk_log2);
     }
 
     if (cache_path && *cache_path) {
@@ -224,8 +231,10 @@ int hamming_tune(const char* cache_path, uint32_t flags, hipStream_t stream)
             fprintf(f, "{\"plain\": %d, \"lane_codewords\": %d, \"max_blocks\": %llu, \"xcd_chunk\": %u, \"us\": %.2f}\n",
                     r, c.u, (unsigned long long)c.max_blocks, c.xcd_chunk, c.us);
         }
-        fprintf(f, "{\"batch\": %d, \"xcd_chunk\": %u, \"grid_cap_blocks\": %u, \"use_graph\": %d, \"ms\": %.3f}\n",
-                batch.schedule, batch.xcd_chunk, batch.grid_cap, batch.use_graph, batch.ms);
+        fprintf(f,
+                "{\"batch\": %d, \"xcd_chunk\": %u, \"grid_cap_blocks\": %u, \"use_graph\": %d, \"chunk_log2\": %u, "
+                "\"ms\": %.3f}\n",
+                batch.schedule, batch.xcd_chunk, batch.grid_cap, batch.use_graph, batch.chunk_log2, batch.ms);
         fclose(f);
     }
     return HAMMING_OK;
@@ -254,6 +263,10 @@ int hamming_tune_load(const char* cache_path)
         } else if (device_ok && sscanf(line, "{\"batch\": %d, \"xcd_chunk\": %u, \"grid_cap_blocks\": %u, \"use_graph\": %d",
                                        &sched, &xc, &cap, &graph) == 4) {
             if (hamming_batch_config_set(sched, xc, cap, graph) == HAMMING_OK) ++applied;
+            // the chunk size is optional (caches written before it existed)
+            const char* c = strstr(line, "\"chunk_log2\": ");
+            unsigned cl = 0;
+            if (c && sscanf(c, "\"chunk_log2\": %u", &cl) == 1) hamming_batch_chunk_set(cl);
         }
     }
     fclose(f);

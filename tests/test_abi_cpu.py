@@ -364,9 +364,11 @@ def test_plain_grid_is_one_wave_per_tile_clamped_to_the_dispatch_limit():
 
 def test_batch_grid_bound_and_clamp():
     old = hm.hamming_batch_config_get()
+    old_chunk = hm.hamming_batch_chunk_get()
     try:
         hm.hamming_batch_config_set(old[0], old[1], 0, old[3])
-        # tiles <= cw_words/256 (or hint/128) + one partial tile per packet
+        hm.hamming_batch_chunk_set(0)
+        # tiles <= cw_words/256 (or hint/128) + one partial tile per packet; one wave per chunk
         assert hm.hamming_decode_batch_grid(1 << 20, 10) == (4096 + 10 + 3) // 4
         assert hm.hamming_decode_batch_grid(1 << 20, 10, 1000) == (7 + 10 + 3) // 4
         assert hm.hamming_decode_batch_grid(1 << 20, 10, 1 << 40) == (4096 + 10 + 3) // 4
@@ -374,10 +376,28 @@ def test_batch_grid_bound_and_clamp():
         assert hm.hamming_decode_batch_grid(1 << 20, 0) == 0
         assert hm.hamming_decode_batch_grid(1 << 20, hm.HAMMING_MAX_BATCH + 1) == 0
         assert hm.hamming_decode_batch_grid(1 << 42, 1000) == DISPATCH_LIMIT_BLOCKS
+        for c in (1, 3, 6):
+            hm.hamming_batch_chunk_set(c)
+            chunks = (4096 + 10 + (1 << c) - 1) >> c
+            assert hm.hamming_decode_batch_grid(1 << 20, 10) == (chunks + 3) // 4
         hm.hamming_batch_config_set(old[0], old[1], 3, old[3])
         assert hm.hamming_decode_batch_grid(1 << 20, 10) == 3
     finally:
         hm.hamming_batch_config_set(*old)
+        hm.hamming_batch_chunk_set(old_chunk)
+
+
+def test_batch_chunk_roundtrip_and_validation():
+    old = hm.hamming_batch_chunk_get()
+    try:
+        for c in range(7):
+            hm.hamming_batch_chunk_set(c)
+            assert hm.hamming_batch_chunk_get() == c
+        with pytest.raises(hm.HammingError):
+            hm.hamming_batch_chunk_set(7)
+        assert hm.hamming_batch_chunk_get() == 6
+    finally:
+        hm.hamming_batch_chunk_set(old)
 
 
 def test_planes_reject_counts_beyond_one_launch():

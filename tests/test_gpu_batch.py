@@ -97,15 +97,19 @@ def test_batch_matches_oracle_and_leaves_gaps(gpu_device, seed):
 @pytest.mark.parametrize("xcd_chunk", [1, 3, 64])
 @pytest.mark.parametrize("grid_cap", [0, 1, 5])
 @pytest.mark.parametrize("use_graph", [0, 1])
-def test_batch_every_schedule_grid_and_launch_mode(gpu_device, schedule, xcd_chunk, grid_cap, use_graph):
+@pytest.mark.parametrize("chunk_log2", [0, 3, 6])
+def test_batch_every_schedule_grid_and_launch_mode(gpu_device, schedule, xcd_chunk, grid_cap, use_graph,
+                                                    chunk_log2):
     import torch
 
     old = hm.hamming_batch_config_get()
-    arena, descs, ys = _build_batch(7 + grid_cap + 10 * xcd_chunk, 40)
+    old_chunk = hm.hamming_batch_chunk_get()
+    arena, descs, ys = _build_batch(7 + grid_cap + 10 * xcd_chunk + 1000 * chunk_log2, 40)
     expect = _expect(ys, descs)
     cw = _to_dev(arena, gpu_device)
     try:
         hm.hamming_batch_config_set(schedule, xcd_chunk, grid_cap, use_graph)
+        hm.hamming_batch_chunk_set(chunk_log2)
         bd = hm.BatchDecoder(cw, 40)
         bd.set_packets(descs)
         s = torch.cuda.Stream()
@@ -116,6 +120,7 @@ def test_batch_every_schedule_grid_and_launch_mode(gpu_device, schedule, xcd_chu
         _check_outputs(bd, descs, expect)
     finally:
         hm.hamming_batch_config_set(*old)
+        hm.hamming_batch_chunk_set(old_chunk)
 
 
 def test_batch_on_default_stream(gpu_device):
@@ -253,23 +258,27 @@ def _decode_with_workspace(gpu_device, arena, descs, ws_bytes, max_codewords=0):
     return bd
 
 
-@pytest.mark.parametrize("fine_log2", [1, 3, 6])
+@pytest.mark.parametrize("chunk_log2,fine_log2", [(0, 1), (0, 3), (0, 6), (2, 3), (3, 6), (1, 1)])
 @pytest.mark.parametrize("schedule", [0, 1, 2, 3])
 @pytest.mark.parametrize("use_graph", [0, 1])
-def test_batch_grouped_fine_map_probe_path(gpu_device, fine_log2, schedule, use_graph):
+def test_batch_grouped_fine_map_probe_path(gpu_device, chunk_log2, fine_log2, schedule, use_graph):
     """A workspace below the recommended size gives a fine map of 2^g tiles
-    per entry; every wave then probes the prefix sums from its entry's packet.
-    The map size is chosen from the batch's tile count so that g is exactly
-    1, 3 or 6, and the outputs must stay byte-exact."""
+    per entry; when an entry spans more than one chunk, every wave probes the
+    prefix sums from its entry's packet.  The map size is chosen from the
+    batch's tile count so that g is exactly fine_log2 (never below the chunk
+    size; equal to it, the map is exact at every chunk start), and the
+    outputs must stay byte-exact."""
     old = hm.hamming_batch_config_get()
-    arena, descs, ys = _build_batch(300 + fine_log2 + 7 * schedule, 60)
+    old_chunk = hm.hamming_batch_chunk_get()
+    arena, descs, ys = _build_batch(300 + fine_log2 + 7 * schedule + 50 * chunk_log2, 60)
     expect = _expect(ys, descs)
     n = descs.size
     try:
         hm.hamming_batch_config_set(schedule, 1, 0, use_graph)
+        hm.hamming_batch_chunk_set(chunk_log2)
         full = _decode_with_workspace(gpu_device, arena, descs, hm.hamming_batch_workspace_bytes(n))
         tiles = full.totals()["tiles"]
-        assert full.totals()["fine_log2"] == 0 and tiles >= 1 << fine_log2
+        assert full.totals()["fine_log2"] == chunk_log2 and tiles >= 1 << fine_log2
         _check_outputs(full, descs, expect, data_fill=0x77, ep_fill=0x88)
         entries = (tiles >> fine_log2) + 1
         ws = hm.hamming_batch_workspace_min_bytes(n) - 4 + 4 * entries
@@ -278,6 +287,7 @@ def test_batch_grouped_fine_map_probe_path(gpu_device, fine_log2, schedule, use_
         _check_outputs(bd, descs, expect, data_fill=0x77, ep_fill=0x88)
     finally:
         hm.hamming_batch_config_set(*old)
+        hm.hamming_batch_chunk_set(old_chunk)
 
 
 @pytest.mark.parametrize("schedule", [0, 2, 3])

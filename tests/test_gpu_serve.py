@@ -332,18 +332,22 @@ def test_serve_trace_scale_results_alone_mix_and_oracle(gpu_device, trace_pool, 
 
 
 @pytest.mark.parametrize("schedule", [0, 1, 2, 3])
-def test_serve_host_plan_many_packets_every_schedule(gpu_device, schedule):
+@pytest.mark.parametrize("chunk_log2", [0, 3, 5])
+def test_serve_host_plan_many_packets_every_schedule(gpu_device, schedule, chunk_log2):
     """Large host-planned batches (hundreds of requests, several with no
     codewords) whose coarse map groups several tiles per entry, under every
-    batch schedule."""
-    rng = np.random.default_rng(70 + schedule)
+    batch schedule and several work chunks (chunks that span many tiny and
+    empty requests)."""
+    rng = np.random.default_rng(70 + schedule + 10 * chunk_log2)
     n = 600
     sizes = [int(rng.choice([0, 1, 63, 64, 65, 300, 1000, 4097, 30000])) for _ in range(n)]
     rs = [int(rng.integers(3, 8)) for _ in range(n)]
-    pool, offs, ys = _pool(30 + schedule, sizes, rs)
+    pool, offs, ys = _pool(30 + schedule + 10 * chunk_log2, sizes, rs)
     cw = _to_dev(pool, gpu_device)
     old = hm.hamming_batch_config_get()
+    old_chunk = hm.hamming_batch_chunk_get()
     hm.hamming_batch_config_set(schedule, 8, 0, old[3])
+    hm.hamming_batch_chunk_set(chunk_log2)
     srv = hm.Server(cw, slots=2, max_batch_packets=300, max_batch_codewords=1 << 30, output_pool_bytes=1 << 30)
     try:
         ids = {srv.submit(offs[i], sizes[i], rs[i]): i for i in range(n)}
@@ -357,3 +361,4 @@ def test_serve_host_plan_many_packets_every_schedule(gpu_device, schedule):
     finally:
         srv.close()
         hm.hamming_batch_config_set(*old)
+        hm.hamming_batch_chunk_set(old_chunk)
