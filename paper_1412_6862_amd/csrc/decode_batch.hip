@@ -292,13 +292,36 @@ void decode_small_batch_kernel(SmallBatch b)
                       lds);
 }
 
+// Last packet p with tile_start[p] <= t, given tile_start[lo] <= t < tile_start[n]
+// (t and lo uniform): eight entries per step by scalar loads, which do not
+// queue behind the wave's streaming vector loads.  The host plan's coarse map
+// puts lo within a packet or two of the answer, so one step almost always
+// suffices.
+__device__ __forceinline__ uint32_t scan_packet(const uint64_t* __restrict__ ts, uint32_t n, uint64_t t, uint32_t lo)
+{
+    for (;;) {
+        // entries lo+1 .. lo+8 at or below t form a prefix (ts is non-decreasing);
+        // indices past n read ts[n] = total > t, so all eight loads issue at once
+        uint64_t e[8];
+#pragma unroll
+        for (uint32_t i = 0; i < 8; ++i) e[i] = ts[min(lo + 1 + i, n)];
+        uint32_t k = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < 8; ++i) k += e[i] <= t ? 1u : 0u;
+        if (k < 8) return lo + k;
+        lo += 8;
+    }
+}
+
 // The host-planned form: chunks of 2^c tiles in order (waves loop when the
 // batch has more chunks than a dispatch can hold), the packet of a chunk's
-// first tile found from the coarse map entry by a 64-lane probe of the prefix
-// sums.
+// first tile found from the coarse map entry by a scalar scan of the prefix
+// sums.  The plan's arrays are separate read-only kernel arguments so that
+// every read of them (map entry, prefix sums, descriptors) is a scalar load.
 template <class S>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(S::waves_per_simd)))
-void decode_planned_batch_kernel(PlannedBatch b)
+void decode_planned_batch_kernel(PlannedBatch b, const uint64_t* __restrict__ ts, const uint32_t* __restrict__ coarse,
+                                 const hamming_packet* __restrict__ descs)
 {
     __shared__ u32x4 lds_raw[kWavesPerBlock][S::LDS_MAX / 4];
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -308,9 +331,9 @@ void decode_planned_batch_kernel(PlannedBatch b)
     for (uint64_t c = uint64_t(xcd_block(blockIdx.x, gridDim.x, b.xcd_chunk)) * kWavesPerBlock + wave;
          (c << cl) < b.total_tiles; c += waves) {
         const uint64_t t = c << cl;
-        const uint32_t p = probe_packet(b.tile_start, b.n, t, b.coarse[t >> b.coarse_log2]);
+        const uint32_t p = scan_packet(ts, b.n, t, coarse[t >> b.coarse_log2]);
         const uint64_t t_end = (t + (uint64_t(1) << cl) < b.total_tiles) ? t + (uint64_t(1) << cl) : b.total_tiles;
-        decode_span<S>(t, t_end, p, b.tile_start, b.descs, b.cw_arena, b.data_arena, b.errpos_arena, lds);
+        decode_span<S>(t, t_end, p, ts, descs, b.cw_arena, b.data_arena, b.errpos_arena, lds);
     }
 }
 
@@ -321,7 +344,8 @@ static hipError_t launch_planned_s(const PlannedBatch& b, hipStream_t stream)
     uint64_t blocks = (chunks + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks > max_launch_blocks(kBlockThreads)) blocks = max_launch_blocks(kBlockThreads);
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((decode_planned_batch_kernel<S>), dim3(uint32_t(blocks)), dim3(kBlockThreads), 0, stream, b);
+    hipLaunchKernelGGL((decode_planned_batch_kernel<S>), dim3(uint32_t(blocks)), dim3(kBlockThreads), 0, stream, b,
+                       b.tile_start, b.coarse, b.descs);
     return hipGetLastError();
 }
 
