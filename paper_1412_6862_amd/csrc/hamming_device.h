@@ -17,6 +17,9 @@
 //
 // Correction (Sec. II, error correction unit): the checksum value s names the
 // flipped position; storage bit s-1 is inverted, branch-free, when s != 0.
+// For r = 6 and 7, s = 0 inverts the top padding bit instead (bit 63 or
+// 127): padding takes no part in the checksum or the extracted message, so
+// the no-error case needs no select.
 //
 // Redundancy removal (Sec. II): the message positions form r-1 runs between
 // consecutive powers of two, run j = positions 2^j+1 .. 2^(j+1)-1; each run
@@ -70,31 +73,33 @@ __device__ __forceinline__ uint32_t push_low_checksum(uint32_t acc, uint32_t f)
     return acc;
 }
 
-// Clear the padding bits (storage bits >= n) of a codeword.
+// Clear the padding bits (storage bits >= n) of a codeword.  For r = 6 the
+// checksum and the extraction below read around the one padding bit, so
+// nothing is cleared.
 template <int R>
 __device__ __forceinline__ void mask_padding(uint32_t (&a)[Code<R>::DW])
 {
     if constexpr (R <= 5) {
         a[0] &= (1u << Code<R>::N) - 1u;
         a[1] = 0;
-    } else if constexpr (R == 6) {
-        a[1] &= kLow31;
-    } else {
+    } else if constexpr (R == 7) {
         a[3] &= kLow31;
     }
 }
 
-// Checksum value s in [0, n] of a codeword whose padding is already clear.
+// Checksum value s in [0, n] of a codeword whose padding is clear (for r = 6:
+// whatever its padding bit holds).
 template <int R>
 __device__ __forceinline__ uint32_t checksum(const uint32_t (&a)[Code<R>::DW])
 {
     if constexpr (R <= 5) {
         return push_low_checksum<R>(0u, a[0]) >> (32 - R);
     } else if constexpr (R == 6) {
+        // bit 31 of the fold is position 32 or 64: outside every set I_0..I_4
         uint32_t acc = push_low_checksum<5>(0u, a[0] ^ a[1]);
         // positions 32..63: bit 31 of dword 0 and bits 0..30 of dword 1
-        // (dword 1's bit 31 is padding and already clear)
-        acc = push_parity(acc, (a[0] & kTop) | a[1]);
+        // (dword 1's bit 31 is padding)
+        acc = push_parity(acc, (a[0] & kTop) | (a[1] & kLow31));
         return acc >> 26;
     } else {
         uint32_t acc = push_low_checksum<5>(0u, a[0] ^ a[1] ^ a[2] ^ a[3]);
@@ -115,15 +120,18 @@ __device__ __forceinline__ void correct(uint32_t (&a)[Code<R>::DW], uint32_t s)
     if constexpr (R <= 5) {
         a[0] ^= (1u << s) >> 1;
     } else if constexpr (R == 6) {
-        const uint64_t v = (uint64_t(1) << s) >> 1;
+        const uint32_t t = s - 1u;                        // s = 0: bit 63, padding
+        const uint64_t v = uint64_t(1) << (t & 63u);
         a[0] ^= uint32_t(v);
         a[1] ^= uint32_t(v >> 32);
     } else {
-        const uint32_t t = s - 1u;             // storage bit; wraps for s == 0
-        const uint32_t bit = 1u << (t & 31u);
-        const uint32_t q = (s == 0u) ? 4u : (t >> 5);
-#pragma unroll
-        for (int w = 0; w < 4; ++w) a[w] ^= (q == uint32_t(w)) ? bit : 0u;
+        const uint32_t t = s - 1u;                        // s = 0: bit 127, padding
+        const uint64_t v = uint64_t(1) << (t & 63u);
+        const uint32_t hi = uint32_t(int32_t(t << 25) >> 31);   // all ones when bit 6 of t is set
+        a[0] ^= uint32_t(v) & ~hi;
+        a[1] ^= uint32_t(v >> 32) & ~hi;
+        a[2] ^= uint32_t(v) & hi;
+        a[3] ^= uint32_t(v >> 32) & hi;
     }
 }
 
@@ -141,9 +149,9 @@ __device__ __forceinline__ void extract(const uint32_t (&a)[Code<R>::DW], uint32
     if constexpr (R <= 5) {
         p[0] = m;
     } else {
-        const uint32_t hi = a[1] & kLow31;     // positions 33..63 (run 5)
+        const uint32_t hi = a[1];              // positions 33..63 (run 5); bit 31 is position 64 or padding
         p[0] = m | (hi << 26);
-        p[1] = hi >> 6;
+        p[1] = bfe(hi, 6, 25);
         if constexpr (R == 7) {                // positions 65..127 (run 6)
             p[1] |= a[2] << 25;
             p[2] = (a[2] >> 7) | (a[3] << 25);

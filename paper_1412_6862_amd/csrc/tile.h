@@ -195,9 +195,12 @@ __device__ __forceinline__ void finish_tile(TileIn<R, U>& tin, uint64_t n_cw, ui
     // Vector j is kept in LDS slot j ^ ((j / NV) % NV): the low bits are
     // rotated per block of NV vectors, so the lane-strided reads below hit
     // different banks while the lane-consecutive writes stay conflict free.
+    // For NV <= 8 (NV^2 divides 64) the rotation of vector 64v + lane does
+    // not depend on v, so one lane address serves every write.
     if (tin.coalesced) {
         u32x4* lv = reinterpret_cast<u32x4*>(lds);
         constexpr uint32_t NV = T::NV;
+        const uint32_t wslot = lane ^ ((lane / NV) % NV);
 #pragma unroll
         for (int v = 0; v < T::NV; ++v) {
             u32x4 x;
@@ -206,13 +209,16 @@ __device__ __forceinline__ void finish_tile(TileIn<R, U>& tin, uint64_t n_cw, ui
             x.z = in[4 * v + 2];
             x.w = in[4 * v + 3];
             const uint32_t j = 64u * v + lane;
-            lv[j ^ ((j / NV) % NV)] = x;
+            if constexpr (NV <= 8)
+                lv[64u * v + wslot] = x;
+            else
+                lv[j ^ ((j / NV) % NV)] = x;
         }
         wave_sync();
 #pragma unroll
         for (int v = 0; v < T::NV; ++v) {
-            const uint32_t j = lane * NV + v;
-            const u32x4 x = lv[j ^ ((j / NV) % NV)];
+            // slot of vector lane*NV + v: lane*NV + (v ^ (lane % NV))
+            const u32x4 x = lv[lane * NV + (uint32_t(v) ^ (lane % NV))];
             in[4 * v + 0] = x.x;
             in[4 * v + 1] = x.y;
             in[4 * v + 2] = x.z;
@@ -264,14 +270,16 @@ __device__ __forceinline__ void finish_tile(TileIn<R, U>& tin, uint64_t n_cw, ui
         e[T::CHW - 1] |= nxt << T::BR;
         e[T::CHW] = nxt >> (32 - T::BR);
     }
-    const uint32_t bitpos = lane * uint32_t(T::B);
+    const uint32_t bitpos = __umul24(lane, uint32_t(T::B));     // lane < 64, B < 2^11
     const uint32_t first = (bitpos + 31u) >> 5;
     const uint32_t a = (first << 5) - bitpos;
     const uint32_t n_own = ((bitpos + T::B + 31u) >> 5) - first;
+    // a chunk of B bits holds floor(B/32) or ceil(B/32) dword starts, so only
+    // the last candidate dword is owned by some lanes and not others
 #pragma unroll
     for (int i = 0; i < T::CHW; ++i) {
         const uint32_t v = (T::BR == 0) ? e[i] : __builtin_amdgcn_alignbit(e[i + 1], e[i], a);
-        if (T::BR == 0 || uint32_t(i) < n_own) lds[first + i] = v;
+        if (T::BR == 0 || i < T::CHW - 1 || uint32_t(i) < n_own) lds[first + i] = v;
     }
     wave_sync();
 
@@ -284,7 +292,7 @@ __device__ __forceinline__ void finish_tile(TileIn<R, U>& tin, uint64_t n_cw, ui
 #pragma unroll
         for (int q = 0; q < (T::WORDS / 2 + 63) / 64; ++q) {
             const uint32_t j = lane + 64u * q;
-            if (j < uint32_t(T::WORDS / 2)) __builtin_nontemporal_store(l4[j], dst + j);
+            if ((q + 1) * 64 <= T::WORDS / 2 || j < uint32_t(T::WORDS / 2)) __builtin_nontemporal_store(l4[j], dst + j);
         }
     } else {
         const uint64_t nw = (data_words - w0 < uint64_t(T::WORDS)) ? (data_words - w0) : uint64_t(T::WORDS);

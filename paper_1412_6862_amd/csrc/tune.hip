@@ -85,6 +85,8 @@ constexpr uint32_t kXcdChoices[] = {1, 8, 32, 128};
 // waves loop over the packet, two tiles in flight per wave (256 CUs hold
 // 2048 workgroups at 8 waves per SIMD).
 constexpr uint64_t kPlainGridChoices[] = {0, 1024, 2048, 4096};
+// Relative time within which plain shapes count as tied.
+constexpr float kPlainTie = 0.015f;
 
 }  // namespace
 
@@ -117,7 +119,7 @@ int hamming_tune(const char* cache_path, uint32_t flags, hipStream_t stream)
         plain[r - 3] = {u0, mb0, xc0, 0.0f};
         if (!do_plain) continue;
         const uint64_t n = r == 7 ? n6 / 2 : n6;
-        float best = 1e30f;
+        std::vector<PlainChoice> tried;
         for (int u : {2, 4, 8, 16}) {
             for (uint32_t xc : kXcdChoices) {
                 for (uint64_t mb : kPlainGridChoices) {
@@ -128,13 +130,22 @@ int hamming_tune(const char* cache_path, uint32_t flags, hipStream_t stream)
                                               static_cast<uint8_t*>(ep.p), stream);
                     }, &ms);
                     if (rc != HAMMING_OK) return rc;
-                    if (ms < best) {
-                        best = ms;
-                        plain[r - 3] = {u, mb, xc, ms * 1000.0f};
-                    }
+                    tried.push_back({u, mb, xc, ms * 1000.0f});
                 }
             }
         }
+        // The plain decode runs at the HBM ceiling with several shapes; among
+        // those within kPlainTie of the fastest, keep the widest lane (the
+        // fewest instructions per codeword, so the most issue headroom), then
+        // the fastest.
+        float best = 1e30f;
+        for (const auto& c : tried) best = c.us < best ? c.us : best;
+        const PlainChoice* pick = nullptr;
+        for (const auto& c : tried) {
+            if (c.us > best * (1.0f + kPlainTie)) continue;
+            if (!pick || c.u > pick->u || (c.u == pick->u && c.us < pick->us)) pick = &c;
+        }
+        if (pick) plain[r - 3] = *pick;
         hamming_plain_config_set(r, plain[r - 3].u, plain[r - 3].max_blocks, plain[r - 3].xcd_chunk);
     }
 
