@@ -652,6 +652,9 @@ def copy_ceiling(dev) -> float:
     return round(2 * (1 << 30) / t[len(t) // 2] / 1e6, 1)
 
 
+_CPUID_KEYS = {"cpu family": "cpu_family", "model": "cpu_model_number", "stepping": "cpu_stepping"}
+
+
 def host_cpu_info() -> dict:
     """CPU model, SMT state and the CPUs this process may run on."""
     info = {"cpu_model": "unknown", "smt": "unknown", "cpus_allowed": None, "host_cpus": os.cpu_count()}
@@ -663,6 +666,9 @@ def host_cpu_info() -> dict:
                 key = key.strip()
                 if key == "model name" and info["cpu_model"] == "unknown":
                     info["cpu_model"] = val.strip()
+                elif key in _CPUID_KEYS and _CPUID_KEYS[key] not in info:
+                    # the numeric identity, for hosts whose model name is generic
+                    info[_CPUID_KEYS[key]] = int(val)
                 elif key == "siblings" and siblings is None:
                     siblings = int(val)
                 elif key == "cpu cores" and cores is None:
@@ -760,8 +766,9 @@ def summary_line(out: dict) -> dict:
         s["hamming74_launch"] = _pick(out["latency_hamming74"], "p50_us", "p99_us")
     if "cpu_baseline" in out:
         cb = out["cpu_baseline"]
-        s["cpu_baseline"] = _pick(cb, "value", "unit", "cores", "kind", "sample", "cpu_model", "smt",
-                                  "cpus_allowed", "single_thread_Gbps_r6", "gpu_over_oracle")
+        s["cpu_baseline"] = _pick(cb, "value", "unit", "cores", "kind", "sample", "cpu_model", "cpu_family",
+                                  "cpu_model_number", "smt", "cpus_allowed", "single_thread_Gbps_r6",
+                                  "gpu_over_oracle")
         s["cpu_baseline"]["paper_speedup_context"] = PAPER_SPEEDUP_CONTEXT
     s["legs"] = sorted(k for k in out if k not in s and k not in ("per_r", "tuned_shapes"))
     # over the limit (never expected): shed the least important fields first

@@ -256,9 +256,11 @@ int hamming_batch_chunk_get(uint32_t *tiles_log2);
 
 /* Workgroups of the batched decode kernel for these arguments of
  * hamming_decode_batch: one wave per chunk (hamming_batch_chunk_set) of the
- * largest batch they allow (min(cw_words/256, max_codewords/128) +
- * max_packets tiles; max_codewords 0 = no hint), capped by grid_cap_blocks
- * and by the 2^32-1 work-items a dispatch can hold.  Host-only and informative; 0 if max_packets is 0 or above
+ * largest batch they allow (min(cw_words/W, max_codewords/C) + max_packets
+ * tiles, W and C the smallest input words and codewords of a tile under the
+ * schedule in force: 256 and 128 for schedules 0-2, 512 and 256 for schedule
+ * 3; max_codewords 0 = no hint), capped by grid_cap_blocks and by the 2^32-1
+ * work-items a dispatch can hold.  Host-only and informative; 0 if max_packets is 0 or above
  * HAMMING_MAX_BATCH. */
 uint64_t hamming_decode_batch_grid(uint64_t cw_words, uint32_t max_packets, uint64_t max_codewords);
 
@@ -471,19 +473,21 @@ int hamming_decode_host(const uint64_t *host_cw, uint64_t n_cw, int r, void *hos
 /*
  * Autotuner: on the current device and `stream`, time the plain decode of
  * random 2^26-codeword packets (2^25 for r = 7) for every lane width, grid
- * cap and XCD chunking, and the batched decode of a batch of up to 2,000
- * packets (sizes log-uniform in [64, 2^20] codewords, r uniform in 3..7,
- * packed into a 2^28-word (2 GiB) codeword arena) for every schedule, XCD
- * chunking and work chunk; apply the fastest shapes (as
+ * cap and XCD chunking, keeping, among the shapes within 1% of the fastest,
+ * the widest lane of at most four 16-byte loads (fewer instructions per
+ * codeword); and the batched decode of two batches in one 2^28-word (2 GiB)
+ * arena of random words, (A) up to 2,000 packets packed end to end (sizes
+ * log-uniform in [64, 2^20] codewords, r uniform in 3..7) and (B) 2,000
+ * requests of a serving mix at random places (sizes log-uniform in
+ * [256, 2^18], r uniform in 4..7), for every schedule, XCD chunking and work
+ * chunk, keeping the one with the least summed time.  Apply the shapes (as
  * hamming_plain_config_set / hamming_batch_config_set /
- * hamming_batch_chunk_set would; a plain shape within 1.5% of the fastest
- * with a wider lane, so fewer instructions per codeword, is preferred) and,
- * when cache_path is neither NULL nor
+ * hamming_batch_chunk_set would) and, when cache_path is neither NULL nor
  * empty, write them there.  flags: bit 0 tunes the plain decode, bit 1 the
  * batched decode.  Allocates up to about 5 GB of device memory for the
  * duration of the call (1.1 GB for the plain trials, the batch arena and its
  * outputs) and synchronises `stream`.  The cache is keyed by the device
- * architecture only: shapes tuned on this batch serve every later batch.
+ * architecture only: shapes tuned on these batches serve every later batch.
  * Returns HAMMING_OK, HAMMING_EINVAL, HAMMING_ENOMEM or HAMMING_EDEVICE.
  */
 int hamming_tune(const char *cache_path, uint32_t flags, hipStream_t stream);

@@ -82,11 +82,6 @@ inline uint32_t batch_fine_capacity(uint32_t max_packets, uint64_t bytes)
     return uint32_t(room < full ? room : full);
 }
 
-// Smallest codeword count of one tile over every r and schedule; sizes the
-// grid from an upper bound on the batch's codewords.
-constexpr uint64_t kMinTileCodewords = 128;
-// Smallest input words of one tile over every r and schedule.
-constexpr uint64_t kMinTileWords = 256;
 // Waves per workgroup of the decode kernels (tile.h's kWavesPerBlock).
 constexpr uint64_t kWavesPerBlockHost = 4;
 
@@ -98,7 +93,7 @@ hipError_t launch_batch(const BatchArgs& a, int schedule, uint32_t grid, hipStre
 int batch_prepare(const uint64_t* cw_arena, uint64_t cw_words, const hamming_packet* descs,
                   const uint32_t* n_packets_dev, uint32_t max_packets, uint64_t max_codewords, uint64_t* data_arena,
                   uint64_t data_words, uint8_t* errpos_arena, uint64_t errpos_bytes, int32_t* status_out,
-                  void* workspace, uint64_t workspace_bytes, BatchArgs* out, uint32_t* grid);
+                  void* workspace, uint64_t workspace_bytes, int schedule, BatchArgs* out, uint32_t* grid);
 
 // The batch schedule in force (hamming_batch_config_set) and the chunk size
 // (hamming_batch_chunk_set).
@@ -157,6 +152,12 @@ hipError_t launch_planned_batch(const PlannedBatch& b, int schedule, hipStream_t
 // Codewords per lane of a tile of r-bit codewords in a batch schedule (a
 // tile is 64 lanes); 0 for an unknown schedule or r.
 uint32_t schedule_lane_width(int schedule, uint32_t r);
+
+// Smallest codeword count and smallest input words of one tile over every r
+// of a schedule: they size the grid from an upper bound on the batch's
+// codewords or input words.
+uint64_t schedule_min_tile_codewords(int schedule);
+uint64_t schedule_min_tile_words(int schedule);
 
 // Decodes a small batch whose tile_start[n] tiles are at least one.
 hipError_t launch_small_batch(const SmallBatch& b, int schedule, hipStream_t stream);

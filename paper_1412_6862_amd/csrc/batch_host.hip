@@ -111,10 +111,11 @@ bool misaligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t
 // Upper bound on the tiles of any batch the arguments allow: the input arena
 // bounds the codewords as well as the caller's hint does, so the tighter of
 // the two is taken, plus one partial tile per packet.
-uint64_t batch_tile_bound(uint64_t cw_words, uint32_t max_packets, uint64_t max_codewords)
+uint64_t batch_tile_bound(uint64_t cw_words, uint32_t max_packets, uint64_t max_codewords, int schedule)
 {
-    uint64_t tiles = cw_words / hm::kMinTileWords;
-    if (max_codewords && max_codewords / hm::kMinTileCodewords < tiles) tiles = max_codewords / hm::kMinTileCodewords;
+    uint64_t tiles = cw_words / hm::schedule_min_tile_words(schedule);
+    const uint64_t min_cw = hm::schedule_min_tile_codewords(schedule);
+    if (max_codewords && max_codewords / min_cw < tiles) tiles = max_codewords / min_cw;
     return tiles + uint64_t(max_packets);
 }
 
@@ -123,10 +124,11 @@ uint64_t batch_tile_bound(uint64_t cw_words, uint32_t max_packets, uint64_t max_
 // but at 4x the count they cost a visible tail), capped by the configured cap
 // and by the dispatch limit, beyond which waves loop over chunks.
 uint64_t batch_grid_blocks(uint64_t cw_words, uint32_t max_packets, uint64_t max_codewords, uint64_t cap,
-                           uint32_t chunk_log2)
+                           uint32_t chunk_log2, int schedule)
 {
-    const uint64_t chunks = (batch_tile_bound(cw_words, max_packets, max_codewords) + (uint64_t(1) << chunk_log2) - 1) >>
-                            chunk_log2;
+    const uint64_t chunks =
+        (batch_tile_bound(cw_words, max_packets, max_codewords, schedule) + (uint64_t(1) << chunk_log2) - 1) >>
+        chunk_log2;
     uint64_t blocks = (chunks + hm::kWavesPerBlockHost - 1) / hm::kWavesPerBlockHost;
     if (cap && blocks > cap) blocks = cap;
     if (blocks > hm::max_launch_blocks(256)) blocks = hm::max_launch_blocks(256);
@@ -142,7 +144,7 @@ namespace hm {
 int batch_prepare(const uint64_t* cw_arena, uint64_t cw_words, const hamming_packet* descs,
                   const uint32_t* n_packets_dev, uint32_t max_packets, uint64_t max_codewords, uint64_t* data_arena,
                   uint64_t data_words, uint8_t* errpos_arena, uint64_t errpos_bytes, int32_t* status_out,
-                  void* workspace, uint64_t workspace_bytes, BatchArgs* out, uint32_t* grid)
+                  void* workspace, uint64_t workspace_bytes, int schedule, BatchArgs* out, uint32_t* grid)
 {
     if (max_packets > HAMMING_MAX_BATCH) return HAMMING_ERANGE;
     if (!cw_arena || !descs || !n_packets_dev || !data_arena || !workspace) return HAMMING_EINVAL;
@@ -172,12 +174,14 @@ int batch_prepare(const uint64_t* cw_arena, uint64_t cw_words, const hamming_pac
     a.coarse = reinterpret_cast<uint32_t*>(a.tile_start + (uint64_t(max_packets) + 1));
     a.fine = a.coarse + a.coarse_cap;
 
-    const uint64_t blocks = batch_grid_blocks(cw_words, max_packets, max_codewords, g_grid_cap.load(), a.chunk_log2);
+    const uint64_t blocks =
+        batch_grid_blocks(cw_words, max_packets, max_codewords, g_grid_cap.load(), a.chunk_log2, schedule);
     *grid = uint32_t(blocks);
     // the fine map has at most one entry per chunk of the bound (its kernel
     // is grid-stride, so this only sizes its grid)
-    const uint64_t chunks = (batch_tile_bound(cw_words, max_packets, max_codewords) + (uint64_t(1) << a.chunk_log2) - 1) >>
-                            a.chunk_log2;
+    const uint64_t chunks =
+        (batch_tile_bound(cw_words, max_packets, max_codewords, schedule) + (uint64_t(1) << a.chunk_log2) - 1) >>
+        a.chunk_log2;
     const uint64_t fine_entries = chunks < a.fine_cap ? chunks : a.fine_cap;
     a.fine_blocks = uint32_t((fine_entries + 255) / 256);
     return HAMMING_OK;
@@ -269,12 +273,13 @@ int hamming_decode_batch(const uint64_t* cw_arena, uint64_t cw_words, const hamm
     if (max_packets == 0) return HAMMING_OK;
     BatchArgs a;
     uint32_t grid = 0;
+    const int schedule = g_schedule.load();
     const int rc = hm::batch_prepare(cw_arena, cw_words, descs, n_packets_dev, max_packets, max_codewords, data_arena,
-                           data_words, errpos_arena, errpos_bytes, status_out, workspace, workspace_bytes, &a, &grid);
+                                     data_words, errpos_arena, errpos_bytes, status_out, workspace, workspace_bytes,
+                                     schedule, &a, &grid);
     if (rc != HAMMING_OK) return rc;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return HAMMING_EDEVICE;
-    const int schedule = g_schedule.load();
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (stream && hipStreamIsCapturing(stream, &cs) != hipSuccess) return HAMMING_EDEVICE;
     if (stream && cs == hipStreamCaptureStatusNone && g_use_graph.load()) {
@@ -306,11 +311,12 @@ int hamming_decode_batch_noalloc(const uint64_t* cw_arena, uint64_t cw_words, co
     if (!ws) return HAMMING_EDEVICE;
     BatchArgs a;
     uint32_t grid = 0;
+    const int schedule = g_schedule.load();
     const int rc = hm::batch_prepare(cw_arena, cw_words, descs, n_packets_dev, max_packets, max_codewords, data_arena,
                                      data_words, errpos_arena, errpos_bytes, status_out, ws,
-                                     HAMMING_NOALLOC_SCRATCH_BYTES, &a, &grid);
+                                     HAMMING_NOALLOC_SCRATCH_BYTES, schedule, &a, &grid);
     if (rc != HAMMING_OK) return rc;
-    return hm::launch_batch(a, g_schedule.load(), grid, stream) == hipSuccess ? HAMMING_OK : HAMMING_EDEVICE;
+    return hm::launch_batch(a, schedule, grid, stream) == hipSuccess ? HAMMING_OK : HAMMING_EDEVICE;
 }
 
 int hamming_batch_release_graphs(void)
@@ -334,7 +340,8 @@ int hamming_batch_release_graphs(void)
 uint64_t hamming_decode_batch_grid(uint64_t cw_words, uint32_t max_packets, uint64_t max_codewords)
 {
     if (max_packets == 0 || max_packets > HAMMING_MAX_BATCH) return 0;
-    return batch_grid_blocks(cw_words, max_packets, max_codewords, g_grid_cap.load(), g_chunk_log2.load());
+    return batch_grid_blocks(cw_words, max_packets, max_codewords, g_grid_cap.load(), g_chunk_log2.load(),
+                             g_schedule.load());
 }
 
 }  // extern "C"

@@ -411,6 +411,26 @@ uint32_t schedule_lane_width(int schedule, uint32_t r)
     }
 }
 
+uint64_t schedule_min_tile_codewords(int schedule)
+{
+    uint64_t m = ~uint64_t(0);
+    for (uint32_t r = 3; r <= 7; ++r) {
+        const uint64_t c = 64ull * schedule_lane_width(schedule, r);
+        if (c && c < m) m = c;
+    }
+    return m == ~uint64_t(0) ? 0 : m;
+}
+
+uint64_t schedule_min_tile_words(int schedule)
+{
+    uint64_t m = ~uint64_t(0);
+    for (uint32_t r = 3; r <= 7; ++r) {
+        const uint64_t c = 64ull * schedule_lane_width(schedule, r) * (r == 7 ? 2 : 1);
+        if (c && c < m) m = c;
+    }
+    return m == ~uint64_t(0) ? 0 : m;
+}
+
 hipError_t launch_batch(const BatchArgs& a, int schedule, uint32_t grid, hipStream_t stream)
 {
     switch (schedule) {

@@ -86,7 +86,7 @@ constexpr uint32_t kXcdChoices[] = {1, 8, 32, 128};
 // 2048 workgroups at 8 waves per SIMD).
 constexpr uint64_t kPlainGridChoices[] = {0, 1024, 2048, 4096};
 // Relative time within which plain shapes count as tied.
-constexpr float kPlainTie = 0.015f;
+constexpr float kPlainTie = 0.01f;
 
 }  // namespace
 
@@ -125,7 +125,7 @@ int hamming_tune(const char* cache_path, uint32_t flags, hipStream_t stream)
                 for (uint64_t mb : kPlainGridChoices) {
                     if (hamming_plain_config_set(r, u, mb, xc) != HAMMING_OK) continue;   // invalid lane width
                     float ms = 0;
-                    const int rc = time_ms(stream, 2, 5, [&] {
+                    const int rc = time_ms(stream, 3, 20, [&] {
                         return hamming_decode(static_cast<const uint64_t*>(cw.p), n, r, data.p,
                                               static_cast<uint8_t*>(ep.p), stream);
                     }, &ms);
@@ -135,15 +135,18 @@ int hamming_tune(const char* cache_path, uint32_t flags, hipStream_t stream)
             }
         }
         // The plain decode runs at the HBM ceiling with several shapes; among
-        // those within kPlainTie of the fastest, keep the widest lane (the
-        // fewest instructions per codeword, so the most issue headroom), then
-        // the fastest.
+        // those within kPlainTie of the fastest, keep the widest lane of at
+        // most four 16-byte loads (the fewest instructions per codeword, so
+        // the most issue headroom, without the register cost of wider lanes),
+        // then the fastest.
         float best = 1e30f;
         for (const auto& c : tried) best = c.us < best ? c.us : best;
+        const int wpc = r == 7 ? 2 : 1;
+        auto width = [&](const PlainChoice& c) { return c.u * wpc <= 8 ? c.u : 0; };
         const PlainChoice* pick = nullptr;
         for (const auto& c : tried) {
             if (c.us > best * (1.0f + kPlainTie)) continue;
-            if (!pick || c.u > pick->u || (c.u == pick->u && c.us < pick->us)) pick = &c;
+            if (!pick || width(c) > width(*pick) || (width(c) == width(*pick) && c.us < pick->us)) pick = &c;
         }
         if (pick) plain[r - 3] = *pick;
         hamming_plain_config_set(r, plain[r - 3].u, plain[r - 3].max_blocks, plain[r - 3].xcd_chunk);
@@ -159,41 +162,52 @@ int hamming_tune(const char* cache_path, uint32_t flags, hipStream_t stream)
         batch.ms = 0;
     }
     if (do_batch) {
-        // a batch shaped like large production batches: 2000 packets, sizes
-        // log-uniform in [64, 2^20] codewords, r uniform in 3..7, in a 2 GiB
-        // arena (the footprint, not only the packet mix, decides the best shape)
+        // Two batches over one 2 GiB arena of random words (the footprint, not
+        // only the packet mix, decides the best shape), and the shape that
+        // minimises their summed time: (A) 2000 packets packed end to end,
+        // sizes log-uniform in [64, 2^20] codewords, r uniform in 3..7, like
+        // large production batches; (B) 2000 requests of a serving mix, sizes
+        // log-uniform in [256, 2^18], r uniform in 4..7, at random places in
+        // the arena.
         const uint32_t np = 2000;
         const uint64_t arena_words = uint64_t(1) << 28;
-        std::vector<hamming_packet> d(np);
-        uint64_t state = 0x6862ull, off = 0, total = 0;
+        uint64_t state = 0x6862ull;
         auto next = [&] {
             state = state * 6364136223846793005ull + 1442695040888963407ull;
             return double(state >> 11) / 9007199254740992.0;
         };
-        uint32_t used = 0;
-        for (uint32_t i = 0; i < np; ++i) {
-            hamming_packet q;
-            memset(&q, 0, sizeof q);
-            q.n_cw = uint64_t(64.0 * std::exp2(14.0 * next()));
-            q.r = 3 + uint32_t(5.0 * next()) % 5;
-            q.in_word_off = off;
-            const uint64_t words = q.n_cw * (q.r == 7 ? 2 : 1);
-            if (off + words > arena_words) break;
-            off += words;
-            total += q.n_cw;
-            d[used++] = q;
+        std::vector<hamming_packet> sets[2];
+        uint64_t totals[2] = {0, 0}, dws[2] = {0, 0}, ebs[2] = {0, 0};
+        for (int k = 0; k < 2; ++k) {
+            uint64_t off = 0;
+            for (uint32_t i = 0; i < np; ++i) {
+                hamming_packet q;
+                memset(&q, 0, sizeof q);
+                if (k == 0) {
+                    q.n_cw = uint64_t(64.0 * std::exp2(14.0 * next()));
+                    q.r = 3 + uint32_t(5.0 * next()) % 5;
+                    q.in_word_off = off;
+                } else {
+                    q.n_cw = uint64_t(256.0 * std::exp2(10.0 * next()));
+                    q.r = 4 + uint32_t(4.0 * next()) % 4;
+                }
+                const uint64_t words = q.n_cw * (q.r == 7 ? 2 : 1);
+                if (k == 1) q.in_word_off = uint64_t(next() * double(arena_words - words));
+                if (q.in_word_off + words > arena_words) break;
+                off += words;
+                totals[k] += q.n_cw;
+                sets[k].push_back(q);
+            }
+            int rc = hamming_batch_layout(sets[k].data(), uint32_t(sets[k].size()), &dws[k], &ebs[k]);
+            if (rc != HAMMING_OK) return rc;
         }
-        d.resize(used);
-        const uint32_t nb = used;
-        uint64_t dw = 0, eb = 0;
-        int rc = hamming_batch_layout(d.data(), nb, &dw, &eb);
-        if (rc != HAMMING_OK) return rc;
-        const uint64_t wsb = hamming_batch_workspace_bytes(nb);
+        const uint64_t dw = dws[0] > dws[1] ? dws[0] : dws[1], eb = ebs[0] > ebs[1] ? ebs[0] : ebs[1];
+        const uint64_t wsb = hamming_batch_workspace_bytes(np);
         e = hipMalloc(&bcw.p, arena_words * 8);
         if (e == hipSuccess) e = hipMalloc(&bdata.p, dw * 8 + 16);
         if (e == hipSuccess) e = hipMalloc(&bep.p, eb + 16);
         if (e == hipSuccess) e = hipMalloc(&ws.p, wsb);
-        if (e == hipSuccess) e = hipMalloc(&descs_dev.p, nb * sizeof(hamming_packet) + 8);
+        if (e == hipSuccess) e = hipMalloc(&descs_dev.p, 2 * (np * sizeof(hamming_packet) + 8));
         if (e != hipSuccess) {
             fprintf(stderr, "hamming_tune: device allocation failed: %s\n", hipGetErrorString(e));
             (void)hipGetLastError();
@@ -202,11 +216,18 @@ int hamming_tune(const char* cache_path, uint32_t flags, hipStream_t stream)
         hipLaunchKernelGGL(fill_random_kernel, dim3(8192), dim3(256), 0, stream, static_cast<uint64_t*>(bcw.p),
                            arena_words, 0x6862ull);
         if (hipGetLastError() != hipSuccess) return HAMMING_EDEVICE;
-        uint32_t* n_dev = static_cast<uint32_t*>(descs_dev.p);
-        auto* dd = reinterpret_cast<hamming_packet*>(static_cast<char*>(descs_dev.p) + 8);
-        if (hipMemcpy(dd, d.data(), nb * sizeof(hamming_packet), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(n_dev, &nb, 4, hipMemcpyHostToDevice) != hipSuccess)
-            return HAMMING_EDEVICE;
+        // per set: its packet count (uint32, 8 bytes reserved) and its descriptors
+        uint32_t* n_dev[2];
+        hamming_packet* dd[2];
+        for (int k = 0; k < 2; ++k) {
+            char* base = static_cast<char*>(descs_dev.p) + k * (np * sizeof(hamming_packet) + 8);
+            n_dev[k] = reinterpret_cast<uint32_t*>(base);
+            dd[k] = reinterpret_cast<hamming_packet*>(base + 8);
+            const uint32_t nk = uint32_t(sets[k].size());
+            if (hipMemcpy(dd[k], sets[k].data(), nk * sizeof(hamming_packet), hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(n_dev[k], &nk, 4, hipMemcpyHostToDevice) != hipSuccess)
+                return HAMMING_EDEVICE;
+        }
         float best = 1e30f;
         for (int sched : {0, 1, 2, 3}) {
             for (uint32_t xc : kXcdChoices) {
@@ -215,16 +236,21 @@ int hamming_tune(const char* cache_path, uint32_t flags, hipStream_t stream)
                     if (hamming_batch_config_set(sched, xc, 0, 0) != HAMMING_OK ||
                         hamming_batch_chunk_set(cl) != HAMMING_OK)
                         return HAMMING_EINVAL;
-                    float ms = 0;
-                    rc = time_ms(stream, 2, 5, [&] {
-                        return hamming_decode_batch(static_cast<const uint64_t*>(bcw.p), off, dd, n_dev, nb, total,
-                                                    static_cast<uint64_t*>(bdata.p), dw, static_cast<uint8_t*>(bep.p),
-                                                    eb, nullptr, ws.p, wsb, stream);
-                    }, &ms);
-                    if (rc != HAMMING_OK) return rc;
-                    if (ms < best) {
-                        best = ms;
-                        batch = {sched, xc, 0, 1, cl, ms};
+                    float sum = 0;
+                    for (int k = 0; k < 2; ++k) {
+                        float ms = 0;
+                        const int rc = time_ms(stream, 2, 5, [&] {
+                            return hamming_decode_batch(static_cast<const uint64_t*>(bcw.p), arena_words, dd[k],
+                                                        n_dev[k], uint32_t(sets[k].size()), totals[k],
+                                                        static_cast<uint64_t*>(bdata.p), dw,
+                                                        static_cast<uint8_t*>(bep.p), eb, nullptr, ws.p, wsb, stream);
+                        }, &ms);
+                        if (rc != HAMMING_OK) return rc;
+                        sum += ms;
+                    }
+                    if (sum < best) {
+                        best = sum;
+                        batch = {sched, xc, 0, 1, cl, sum};
                     }
                 }
             }

@@ -366,7 +366,7 @@ def test_batch_grid_bound_and_clamp():
     old = hm.hamming_batch_config_get()
     old_chunk = hm.hamming_batch_chunk_get()
     try:
-        hm.hamming_batch_config_set(old[0], old[1], 0, old[3])
+        hm.hamming_batch_config_set(2, old[1], 0, old[3])
         hm.hamming_batch_chunk_set(0)
         # tiles <= cw_words/256 (or hint/128) + one partial tile per packet; one wave per chunk
         assert hm.hamming_decode_batch_grid(1 << 20, 10) == (4096 + 10 + 3) // 4
@@ -380,7 +380,12 @@ def test_batch_grid_bound_and_clamp():
             hm.hamming_batch_chunk_set(c)
             chunks = (4096 + 10 + (1 << c) - 1) >> c
             assert hm.hamming_decode_batch_grid(1 << 20, 10) == (chunks + 3) // 4
-        hm.hamming_batch_config_set(old[0], old[1], 3, old[3])
+        # schedule 3: every tile holds at least 256 codewords in 512 words
+        hm.hamming_batch_chunk_set(0)
+        hm.hamming_batch_config_set(3, old[1], 0, old[3])
+        assert hm.hamming_decode_batch_grid(1 << 20, 10) == (2048 + 10 + 3) // 4
+        assert hm.hamming_decode_batch_grid(1 << 20, 10, 1000) == (3 + 10 + 3) // 4
+        hm.hamming_batch_config_set(2, old[1], 3, old[3])
         assert hm.hamming_decode_batch_grid(1 << 20, 10) == 3
     finally:
         hm.hamming_batch_config_set(*old)
