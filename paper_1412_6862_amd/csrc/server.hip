@@ -46,6 +46,9 @@ constexpr uint64_t kAlign = 256;   // output allocations start on 256-byte bound
 // 224-242 us.
 constexpr uint64_t kDirectMaxCodewords = uint64_t(1) << 20;
 
+// Arrivals a trace replay submits between two progress calls.
+constexpr uint32_t kSubmitBurst = 256;
+
 uint64_t round_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
 uint64_t now_ns()
@@ -456,7 +459,10 @@ int run_trace_loop(hamming_server* s, uint32_t n, const uint64_t* arrival_ns, co
     while (finished < n) {
         const uint64_t t = now_ns();
         if (t - start > timeout_ns) return HAMMING_ERANGE;
-        while (next < n && arrival_ns[next] <= t - start) {
+        // at most kSubmitBurst arrivals between two progress calls, so a
+        // burst of arrivals (a saturated trace has all of them at time 0)
+        // does not hold back the first launches
+        for (uint32_t burst = 0; burst < kSubmitBurst && next < n && arrival_ns[next] <= t - start; ++burst) {
             uint64_t id = 0;
             const int rc = hamming_server_submit(s, in_word_off[next], n_cw[next], r[next], start + arrival_ns[next],
                                                  &id);

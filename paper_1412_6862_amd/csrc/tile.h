@@ -117,27 +117,27 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Input registers of one lane for one tile.  With `coalesced` set, in[] holds
-// the lane's 16-byte vectors v*64 + lane of the tile (consecutive lanes read
-// consecutive vectors); finish_tile transposes them through LDS.  Otherwise
-// in[] already holds the lane's own U codewords.
+// Input registers of one lane for one tile: the lane's 16-byte vectors
+// v*64 + lane of the tile (consecutive lanes read consecutive vectors);
+// finish_tile transposes them through LDS to the lane's own U codewords.
 template <int R, int U>
 struct TileIn {
     uint32_t in[U * Code<R>::DW];
-    bool coalesced;
 };
 
-// Issue the loads of tile `tile` (codewords past n_cw read as zero).
+// Issue the loads of tile `tile`.  In the ragged last tile of a packet the
+// vectors past its last codeword read as zero (a vector holding only the
+// last word is read as one 8-byte load), so every access stays inside the
+// packet and the tile still goes through the coalesced transpose.
 template <int R, int U>
 __device__ __forceinline__ void load_tile(const uint64_t* __restrict__ cw, uint64_t n_cw, uint64_t tile,
                                           uint32_t lane, TileIn<R, U>& t)
 {
     using C = Code<R>;
     using T = TileShape<R, U>;
-    const bool full = (tile + 1) * T::CW <= n_cw;
-    t.coalesced = full;
-    if (t.coalesced) {
-        const u32x4a8* src = reinterpret_cast<const u32x4a8*>(cw + tile * T::CW * C::WPC) + lane;
+    const uint64_t w0 = tile * T::CW * C::WPC;          // first input word of the tile
+    const u32x4a8* src = reinterpret_cast<const u32x4a8*>(cw + w0) + lane;
+    if ((tile + 1) * T::CW <= n_cw) {
 #pragma unroll
         for (int v = 0; v < T::NV; ++v) {
             const u32x4 x = __builtin_nontemporal_load(src + 64 * v);
@@ -147,15 +147,22 @@ __device__ __forceinline__ void load_tile(const uint64_t* __restrict__ cw, uint6
             t.in[4 * v + 3] = x.w;
         }
     } else {
-        const uint64_t c0 = tile * T::CW + uint64_t(lane) * U;
+        const uint64_t rem = n_cw * C::WPC - w0;          // input words left in the packet, < the tile's
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-#pragma unroll
-            for (int q = 0; q < C::WPC; ++q) {
-                const uint64_t x = (c0 + u < n_cw) ? cw[(c0 + u) * C::WPC + q] : 0;
-                t.in[u * C::DW + 2 * q] = uint32_t(x);
-                t.in[u * C::DW + 2 * q + 1] = uint32_t(x >> 32);
+        for (int v = 0; v < T::NV; ++v) {
+            const uint64_t w = 2 * (64u * uint64_t(v) + lane);   // first word of this lane's vector v
+            u32x4 x = {0u, 0u, 0u, 0u};
+            if (w + 1 < rem) {
+                x = __builtin_nontemporal_load(src + 64 * v);
+            } else if (w < rem) {
+                const uint64_t y = cw[w0 + w];
+                x.x = uint32_t(y);
+                x.y = uint32_t(y >> 32);
             }
+            t.in[4 * v + 0] = x.x;
+            t.in[4 * v + 1] = x.y;
+            t.in[4 * v + 2] = x.z;
+            t.in[4 * v + 3] = x.w;
         }
     }
 }
@@ -168,7 +175,6 @@ __device__ __forceinline__ void load_full_tile(const uint64_t* __restrict__ cw, 
 {
     using C = Code<R>;
     using T = TileShape<R, U>;
-    t.coalesced = true;
     const u32x4a8* src = reinterpret_cast<const u32x4a8*>(cw + tile * T::CW * C::WPC) + lane;
 #pragma unroll
     for (int v = 0; v < T::NV; ++v) {
@@ -197,7 +203,7 @@ __device__ __forceinline__ void finish_tile(TileIn<R, U>& tin, uint64_t n_cw, ui
     // different banks while the lane-consecutive writes stay conflict free.
     // For NV <= 8 (NV^2 divides 64) the rotation of vector 64v + lane does
     // not depend on v, so one lane address serves every write.
-    if (tin.coalesced) {
+    {
         u32x4* lv = reinterpret_cast<u32x4*>(lds);
         constexpr uint32_t NV = T::NV;
         const uint32_t wslot = lane ^ ((lane / NV) % NV);
@@ -236,8 +242,10 @@ __device__ __forceinline__ void finish_tile(TileIn<R, U>& tin, uint64_t n_cw, ui
     decode_lane_codewords<R, U, 0>(in, chunk, s);
 
     // ---- error positions ---------------------------------------------------
+    // lanes whose U codewords all exist store them at once (every lane of a
+    // full tile; in the ragged tile all but the lanes past its end)
     if (errpos) {
-        if (full && (flags & kFlagEpVec)) {
+        if ((flags & kFlagEpVec) && c0 + U <= n_cw) {
             if constexpr (U == 2) {
                 *reinterpret_cast<uint16_t*>(errpos + c0) = uint16_t(s[0] | (s[1] << 8));
             } else {
@@ -295,15 +303,19 @@ __device__ __forceinline__ void finish_tile(TileIn<R, U>& tin, uint64_t n_cw, ui
             if ((q + 1) * 64 <= T::WORDS / 2 || j < uint32_t(T::WORDS / 2)) __builtin_nontemporal_store(l4[j], dst + j);
         }
     } else {
+        // ragged tile: whole 16-byte vectors below the stream's end, then at
+        // most one last 64-bit word
         const uint64_t nw = (data_words - w0 < uint64_t(T::WORDS)) ? (data_words - w0) : uint64_t(T::WORDS);
-        const uint2* l2 = reinterpret_cast<const uint2*>(lds);
+        const u32x4* l4 = reinterpret_cast<const u32x4*>(lds);
+        u32x4a8* dst = reinterpret_cast<u32x4a8*>(data + w0);
 #pragma unroll
-        for (int q = 0; q < (T::WORDS + 63) / 64; ++q) {
+        for (int q = 0; q < (T::WORDS / 2 + 63) / 64; ++q) {
             const uint32_t j = lane + 64u * q;
-            if (j < nw) {
-                const uint2 v = l2[j];
-                __builtin_nontemporal_store(uint64_t(v.x) | (uint64_t(v.y) << 32), data + w0 + j);
-            }
+            if (2 * uint64_t(j) + 1 < nw) __builtin_nontemporal_store(l4[j], dst + j);
+        }
+        if ((nw & 1) && lane == 0) {
+            const uint2 v = reinterpret_cast<const uint2*>(lds)[nw - 1];
+            __builtin_nontemporal_store(uint64_t(v.x) | (uint64_t(v.y) << 32), data + w0 + nw - 1);
         }
     }
     wave_sync();
