@@ -32,6 +32,8 @@ using hm::head_expand;
 using hm::head_message;
 using hm::mask_top;
 using hm::run_start;
+using hm::u32x4;
+using hm::u32x4a8;
 using hm::wave_sync;
 
 namespace {
@@ -48,10 +50,11 @@ __host__ __device__ inline uint32_t enc_slice_words(uint32_t max_msg_bytes)
 }
 
 // Message words of the longest packet plus three (a message run ORed in at a
-// bit offset touches up to three words).
+// bit offset touches up to three words) plus one (the buffer is cleared in
+// pairs of words).
 __host__ __device__ inline uint32_t msg_slice_words(uint32_t max_msg_bytes)
 {
-    return (max_msg_bytes + 7u) / 8u + 3u;
+    return (max_msg_bytes + 7u) / 8u + 4u;
 }
 
 // Checksum bits of a shortened segment with k >= 1 message bits: the
@@ -366,7 +369,10 @@ __device__ __forceinline__ void decode_packet(const SegArgs& a, uint64_t pk, uin
     }
     uint64_t* X = acc;
     uint32_t* H = reinterpret_cast<uint32_t*>(acc + HAMMING_SEG_MAX_T);
-    for (uint32_t w = gl; w < mw + 3; w += GROUP) Mb[w] = 0;
+    for (uint32_t w = 2 * gl; w < mw + 3; w += 2 * GROUP) {   // in pairs: the slice has mw + 4 words
+        Mb[w] = 0;
+        Mb[w + 1] = 0;
+    }
     for (uint32_t i = gl; i < t; i += GROUP) {
         X[i] = 0;
         H[i] = 0;
@@ -402,8 +408,19 @@ __device__ __forceinline__ void decode_packet(const SegArgs& a, uint64_t pk, uin
     if (a.status && gl == 0) a.status[pk] = any2 ? 2 : (any1 ? 1 : 0);
     group_sync<GROUP>();
 
+    // the message words in 16-byte stores (two words per thread and step)
     uint64_t* dst = a.msg + d.msg_word_off;
-    for (uint32_t ow = gl; ow < mw; ow += GROUP) __builtin_nontemporal_store(Mb[ow], dst + ow);
+    const uint64_t pairs = mw / 2;
+    for (uint32_t q = gl; q < pairs; q += GROUP) {
+        const uint64_t w0 = Mb[2 * q], w1 = Mb[2 * q + 1];
+        u32x4 v;
+        v.x = uint32_t(w0);
+        v.y = uint32_t(w0 >> 32);
+        v.z = uint32_t(w1);
+        v.w = uint32_t(w1 >> 32);
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x4a8*>(dst) + q);
+    }
+    if ((mw & 1) && gl == 0) __builtin_nontemporal_store(Mb[mw - 1], dst + mw - 1);
 }
 
 // Encode packet pk with GROUP threads; E is the packet's encoded buffer in
@@ -443,8 +460,19 @@ __device__ __forceinline__ void encode_packet(const SegArgs& a, uint64_t pk, uin
     }
     group_sync<GROUP>();
 
+    // the encoded words in 16-byte stores (two words per thread and step)
     uint64_t* dst = const_cast<uint64_t*>(a.enc) + d.enc_word_off;
-    for (uint32_t w = gl; w < ew; w += GROUP) __builtin_nontemporal_store(E[w + 1], dst + w);
+    const uint64_t pairs = ew / 2;
+    for (uint32_t q = gl; q < pairs; q += GROUP) {
+        const uint64_t w0 = E[2 * q + 1], w1 = E[2 * q + 2];
+        u32x4 v;
+        v.x = uint32_t(w0);
+        v.y = uint32_t(w0 >> 32);
+        v.z = uint32_t(w1);
+        v.w = uint32_t(w1 >> 32);
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x4a8*>(dst) + q);
+    }
+    if ((ew & 1) && gl == 0) __builtin_nontemporal_store(E[ew], dst + ew - 1);
 }
 
 // 256 / GROUP packets per block, GROUP threads each: part of a wave, a wave,

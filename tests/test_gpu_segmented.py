@@ -254,6 +254,34 @@ def test_segmented_segments_ending_at_window_boundaries(gpu_device, seg_mode, ms
     assert np.array_equal(b.enc.cpu().numpy().view(np.uint8).reshape(P, -1), clean)
 
 
+def _long_segment_edge_shapes():
+    """(M, t) shapes whose segments all have at least 256 positions and end
+    at given places of their last 128-position window: n mod 128 = 0 (a last
+    window of one position), 1, 2, 63, 64, 65, 126, 127; first found, M in
+    32..800."""
+    found = {}
+    for M in range(32, 801):
+        for t in range(1, 7):
+            if 8 * M < t:
+                continue
+            n = oracle.seg_layout(M, t)[2]
+            if min(n) < 256:
+                continue
+            for x in n:
+                if x % 128 in (0, 1, 2, 63, 64, 65, 126, 127) and x % 128 not in found:
+                    found[x % 128] = (M, t)
+    assert len(found) == 8, found
+    return sorted(set(found.values()))
+
+
+@pytest.mark.parametrize("seg_mode", MODES, indirect=True)
+@pytest.mark.parametrize("msg_bytes,t", _long_segment_edge_shapes())
+def test_segmented_long_segments_ending_at_window_boundaries(gpu_device, seg_mode, msg_bytes, t):
+    # a short last window of a long segment, followed by the next segment's
+    # window 0, in every group size
+    _check_batch(gpu_device, 257, msg_bytes, t, p_single=0.5, p_double=0.2)
+
+
 @pytest.mark.parametrize("seg_mode", MODES, indirect=True)
 def test_segmented_max_msg_bytes_bound_rejects_longer_packets(gpu_device, seg_mode):
     import torch
