@@ -282,6 +282,65 @@ def test_segmented_long_segments_ending_at_window_boundaries(gpu_device, seg_mod
     _check_batch(gpu_device, 257, msg_bytes, t, p_single=0.5, p_double=0.2)
 
 
+def _message_boundary_shapes():
+    """(M, t) shapes whose segments carry at least 128 message bits, chosen
+    so that the segment boundaries K_j mod 64 (where a segment's message run
+    starts in the merged message words) and the packet end 8M mod 64 take the
+    values 0 (a word start), 1, 7, 8, 56, 57 (the 57 head bits end on a word
+    boundary) and 63; plus 128-bit segments (also with t = 32), 127-bit ones
+    and single-segment packets."""
+    want = {0, 1, 7, 8, 56, 57, 63}
+    found_k, found_end = {}, {}
+    for M in range(16, 700):
+        for t in range(2, 7):
+            k = oracle.seg_layout(M, t)[0]
+            if min(k) < 128:
+                continue
+            K = np.cumsum(k)[:-1]
+            for x in K % 64:
+                if x in want and x not in found_k:
+                    found_k[int(x)] = (M, t)
+            e = (8 * M) % 64
+            if e in want and e not in found_end:
+                found_end[e] = (M, t)
+    assert set(found_k) == want and set(found_end) == {0, 8, 56}, (found_k, found_end)
+    extra = [(512, 32), (16, 1), (400, 1), (4096, 32), (508, 32), (160, 10), (159, 10)]
+    return sorted(set(found_k.values()) | set(found_end.values()) | set(extra))
+
+
+@pytest.mark.parametrize("seg_mode", MODES, indirect=True)
+@pytest.mark.parametrize("msg_bytes,t", _message_boundary_shapes())
+def test_segmented_segment_boundaries_at_every_word_offset(gpu_device, seg_mode, msg_bytes, t):
+    _check_batch(gpu_device, 131, msg_bytes, t, p_single=0.5, p_double=0.2)
+
+
+@pytest.mark.parametrize("seg_mode", [8, 16, 256], indirect=True)
+@pytest.mark.parametrize("msg_bytes,t", [(200, 3), (40, 2), (33, 2)])
+def test_segmented_every_single_error_position(gpu_device, seg_mode, msg_bytes, t):
+    """Packet i carries one flip at stream bit i, for every bit of the packet:
+    each position of each segment (checksum positions, head positions, the
+    last position) is corrected or reported exactly as the oracle does."""
+    import torch
+
+    _, _, n, bits = oracle.seg_layout(msg_bytes, t)
+    P = int(bits)
+    b = hm.SegmentedBatch(P, msg_bytes, t, device=gpu_device)
+    seed = synth.workload_seed("gpu-seg-every-position", msg_bytes, t)
+    msgs = synth.packet_bytes(seed, P, msg_bytes)
+    enc = oracle.seg_encode_many(msgs, t, row_bytes=b.enc_stride * 8)
+    rows = np.arange(P)
+    enc[rows, rows // 8] ^= (1 << (rows % 8)).astype(np.uint8)
+    b.enc.copy_(torch.from_numpy(np.ascontiguousarray(enc).reshape(-1).view(np.int64)).to(gpu_device))
+    b.decode()
+    torch.cuda.synchronize()
+    m_ref, s_ref, st_ref = oracle.seg_decode_many(enc, msg_bytes, t)
+    assert np.array_equal(m_ref, msgs)          # every single flip is corrected
+    got = b.msg.cpu().numpy().view(np.uint8).reshape(P, -1)[:, :msg_bytes]
+    assert np.array_equal(got, m_ref)
+    assert np.array_equal(b.syndromes.cpu().numpy().view(np.uint16).reshape(P, t), s_ref)
+    assert np.array_equal(b.status.cpu().numpy(), st_ref)
+
+
 @pytest.mark.parametrize("seg_mode", MODES, indirect=True)
 def test_segmented_max_msg_bytes_bound_rejects_longer_packets(gpu_device, seg_mode):
     import torch
