@@ -505,14 +505,14 @@ __global__ __launch_bounds__(64 * kSegWaves) void seg_encode_kernel(SegArgs a)
 constexpr uint32_t kWideMaxPackets = 2048;
 std::atomic<uint32_t> g_seg_threads{0};
 
-uint32_t auto_threads_per_packet(uint32_t n_packets, uint32_t max_msg_bytes)
+uint32_t auto_threads_per_packet(uint32_t n_packets, uint32_t max_msg_bytes, bool decode)
 {
     if (n_packets <= kWideMaxPackets) return 256;
-    // measured on the Table 1 grid (400..2000-byte packets): 8 threads per
-    // packet are fastest at 400 bytes (the per-packet overhead is shared by
-    // eight packets of a wave), tie with 16 at 800, and 16 beat 8, 32 and 64
-    // from 1200 bytes on
-    if (max_msg_bytes <= 640) return 8u;
+    // measured on the Table 1 grid (400..2000-byte packets) and between its
+    // sizes: 8 threads per packet are fastest at 400 bytes (the per-packet
+    // overhead is shared by eight packets of a wave) and, decoding, at 640
+    // and 800 bytes for every t; 16 beat 8, 32 and 64 from 1000 bytes on
+    if (max_msg_bytes <= (decode ? 896u : 640u)) return 8u;
     return max_msg_bytes <= 2048 ? 16u : (max_msg_bytes <= 3072 ? 32u : 64u);
 }
 
@@ -533,7 +533,7 @@ template <bool DECODE>
 void launch(const SegArgs& a, uint32_t n_packets, uint32_t max_msg_bytes, hipStream_t stream)
 {
     uint32_t group = g_seg_threads.load();
-    if (group == 0) group = auto_threads_per_packet(n_packets, max_msg_bytes);
+    if (group == 0) group = auto_threads_per_packet(n_packets, max_msg_bytes, DECODE);
     const bool deep = (8u * max_msg_bytes) / (128u * group) > 5u;
     void (*kernel)(SegArgs);
     if (group == 8)

@@ -353,11 +353,12 @@ def test_segmented_max_msg_bytes_bound_rejects_longer_packets(gpu_device, seg_mo
     assert (b.status.cpu().numpy() == hm.HAMMING_SEG_INVALID).all()
 
 
-@pytest.mark.parametrize("P,mb,t", [(1 << 20, 1500, 4), (1 << 19, 400, 6), (1 << 19, 1200, 4), (1 << 19, 2000, 6)])
+@pytest.mark.parametrize("P,mb,t", [(1 << 20, 1500, 4), (1 << 19, 400, 6), (1 << 19, 800, 3), (1 << 19, 1200, 4),
+                                    (1 << 19, 2000, 6)])
 def test_segmented_full_size_sampled(gpu_device, P, mb, t):
     """Full-size batches in the library's own launch choice (the Table 1 grid
-    is decoded with 2^19 packets per shape: 400 bytes take 8 threads per
-    packet, 1200 and 2000 bytes 16, with two and four windows loaded ahead),
+    is decoded with 2^19 packets per shape: 400 and 800 bytes take 8 threads
+    per packet, 1200 and 2000 bytes 16, with two or four windows loaded ahead),
     encoded on the GPU; a sample of packets is checked against the oracle one
     by one."""
     import torch
