@@ -721,8 +721,9 @@ def cpu_baseline(log2_sample: int):
         "unit": "Gbit/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": "2^%d codewords of each of r=4,5,6 (p=%.2f), %d threads, decode only, %.2f s; one thread "
-                  "on a 2^22-codeword slice of r=6" % (log2_sample, P_SINGLE, threads, elapsed),
+        "sample": "2^%d codewords of each of r=4,5,6 (p=%.2f), %d threads, decode only, %.2f s (%.1f thread-s); "
+                  "one thread on a 2^22-codeword slice of r=6" % (log2_sample, P_SINGLE, threads, elapsed,
+                                                                   elapsed * threads),
         "single_thread_Gbps_r6": round(single, 3),
     }
     out.update(host_cpu_info())
@@ -792,7 +793,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--log2-cw", type=int, default=WORKLOAD_LOG2)
-    ap.add_argument("--cpu-log2", type=int, default=24)
+    # 2^25 codewords of each of the three r: about 20 thread-seconds of oracle work on 16 host threads
+    ap.add_argument("--cpu-log2", type=int, default=25)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--batch-packets", type=int, default=20000)
     ap.add_argument("--serve-requests", type=int, default=100000)
