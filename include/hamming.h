@@ -545,8 +545,11 @@ uint64_t hamming_server_now_ns(void);
  * and its size is the admission cap.  Both stay owned by the caller and must
  * outlive the server.  The server allocates per-slot streams, descriptor
  * arrays, pinned staging and workspaces; hamming_server_destroy frees them.
- * Returns HAMMING_OK, HAMMING_EINVAL (bad config, NULL pointer),
- * HAMMING_EALIGN, HAMMING_ENOMEM or HAMMING_EDEVICE.
+ * Before returning it runs an empty kernel of the batched decode's code
+ * object and waits for it, so that loading that object (once per process) is
+ * not charged to the first batch.  Returns HAMMING_OK, HAMMING_EINVAL (bad
+ * config, NULL pointer), HAMMING_EALIGN, HAMMING_ENOMEM or HAMMING_EDEVICE
+ * (the start-up launch failed).
  */
 int hamming_server_create(const hamming_server_config *config, const uint64_t *cw_pool,
                           uint64_t cw_pool_words, void *output_pool, uint64_t output_pool_bytes,

@@ -162,4 +162,9 @@ uint64_t schedule_min_tile_words(int schedule);
 // Decodes a small batch whose tile_start[n] tiles are at least one.
 hipError_t launch_small_batch(const SmallBatch& b, int schedule, hipStream_t stream);
 
+// Launches an empty kernel from the batched decode's code object: the first
+// launch of any kernel of that object in a process loads it (about 1.2 ms),
+// so a server does this at creation rather than in its first batch.
+hipError_t launch_batch_module_start(hipStream_t stream);
+
 }  // namespace hm

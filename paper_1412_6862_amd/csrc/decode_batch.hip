@@ -387,6 +387,14 @@ static hipError_t launch_small_s(const SmallBatch& b, hipStream_t stream)
     return hipGetLastError();
 }
 
+__global__ void batch_module_start_kernel() {}
+
+hipError_t launch_batch_module_start(hipStream_t stream)
+{
+    hipLaunchKernelGGL(batch_module_start_kernel, dim3(1), dim3(64), 0, stream);
+    return hipGetLastError();
+}
+
 hipError_t launch_small_batch(const SmallBatch& b, int schedule, hipStream_t stream)
 {
     if (b.n < 1 || b.n > kSmallBatchMax) return hipErrorInvalidValue;

@@ -342,6 +342,13 @@ int hamming_server_create(const hamming_server_config* config, const uint64_t* c
             return HAMMING_ENOMEM;
         }
     }
+    // the batch kernels' code object is loaded here, not in the first batch
+    if (hm::launch_batch_module_start(s->slots[0].stream) != hipSuccess ||
+        hipStreamSynchronize(s->slots[0].stream) != hipSuccess) {
+        (void)hipGetLastError();
+        free_server(s);
+        return HAMMING_EDEVICE;
+    }
     *out = s;
     return HAMMING_OK;
 }
