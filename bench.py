@@ -581,7 +581,7 @@ def segmented_leg(dev, n_packets: int, reps: int, lat_reps: int, shapes=None):
         b = hm.SegmentedBatch(n_packets, mb, t, device=dev)
         seed = synth.workload_seed("bench-seg", mb, t)
         b.msg.copy_(synth.draws_torch(seed, 0, n_packets * b.msg_stride, dev))
-        t_enc = time_events(lambda: b.encode(stream), stream, 3, reps)
+        t_enc = time_events(lambda: b.encode(stream), stream, 10, reps)
         enc_med = t_enc[len(t_enc) // 2]
         k, r, _ = hm.hamming_seg_layout(mb, t)
         n = np.asarray(k) + np.asarray(r)
@@ -592,7 +592,7 @@ def segmented_leg(dev, n_packets: int, reps: int, lat_reps: int, shapes=None):
         one = torch.ones_like(bits)
         b.enc ^= torch.zeros_like(b.enc).scatter_add_(0, bits // 64, torch.bitwise_left_shift(one, bits % 64))
         del bits, one
-        t_batch = time_events(lambda: b.decode(stream), stream, 3, reps)
+        t_batch = time_events(lambda: b.decode(stream), stream, 10, reps)
         med = t_batch[len(t_batch) // 2]
         algo = segmented_algorithmic_bytes(mb, t) * n_packets
         lat = np.array(time_events(lambda: hm.hamming_decode_segmented(
@@ -973,7 +973,9 @@ def main() -> int:
         shapes = SEG_SHAPES
         if args.seg_shapes:
             shapes = [tuple(int(v) for v in s.split("/")) for s in args.seg_shapes.split(",")]
-        run_leg("segmented", segmented_leg, dev, args.seg_packets, 5, 200, shapes)
+        # 20 timed launches after 10 untimed ones per shape: consecutive launches of one shape vary
+        # by up to 15%, so a median of 5 moved between runs by as much
+        run_leg("segmented", segmented_leg, dev, args.seg_packets, 20, 200, shapes)
     if not args.no_cpu:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(args.cpu_log2)
