@@ -480,11 +480,13 @@ int hamming_decode_host(const uint64_t *host_cw, uint64_t n_cw, int r, void *hos
  * log-uniform in [64, 2^20] codewords, r uniform in 3..7) and (B) 2,000
  * requests of a serving mix at random places (sizes log-uniform in
  * [256, 2^18], r uniform in 4..7), for every schedule, XCD chunking and work
- * chunk, keeping the one with the least summed time.  Apply the shapes (as
- * hamming_plain_config_set / hamming_batch_config_set /
- * hamming_batch_chunk_set would) and, when cache_path is neither NULL nor
- * empty, write them there.  flags: bit 0 tunes the plain decode, bit 1 the
- * batched decode.  Allocates up to about 5 GB of device memory for the
+ * chunk; the shapes within 3% of the least summed time (at most 8) are timed
+ * twice more with 20 launches per batch, and the lowest mean of those is
+ * kept.  Apply the shapes (as hamming_plain_config_set /
+ * hamming_batch_config_set / hamming_batch_chunk_set would) and, when
+ * cache_path is neither NULL nor empty, write them there (a shape not tuned
+ * by this call is written as it stands, with the time hamming_tune_load read
+ * for it).  flags: bit 0 tunes the plain decode, bit 1 the batched decode.  Allocates up to about 5 GB of device memory for the
  * duration of the call (1.1 GB for the plain trials, the batch arena and its
  * outputs) and synchronises `stream`.  The cache is keyed by the device
  * architecture only: shapes tuned on these batches serve every later batch.
@@ -508,7 +510,10 @@ int hamming_tune_load(const char *cache_path);
  * the kernel arguments.  A larger one is planned on the host, which validated
  * every request at submission: the tile prefix sums and a coarse
  * tile-to-packet map go to the device with the descriptors in one copy, and
- * one decode launch follows (no planning or map kernels).  A request is
+ * one decode launch follows (no planning or map kernels).  Served batches use
+ * the schedule of hamming_batch_config_set and an XCD chunk of 16 of their
+ * own (measured on served traffic; the configured chunk is the graph-batched
+ * path's).  A request is
  * admitted when its outputs fit in the server's output pool (the
  * device-memory admission cap); until then it waits in FIFO order.
  * The server is driven by the caller (hamming_server_progress) and keeps no

@@ -39,12 +39,20 @@ constexpr uint64_t kAlign = 256;   // output allocations start on 256-byte bound
 
 // Batches of at most hm::kSmallBatchMax requests and this many codewords are
 // decoded in one launch with their descriptors in the kernel arguments;
-// others go through hamming_decode_batch.  Measured on the serving trace of
+// others are planned on the host and decoded by one planned-batch launch.  Measured on the serving trace of
 // the bench (256 streams, requests of 256..2^18 codewords): p50 at 10% load
 // 22-31 us against 63-70 us; without the codeword bound the one-launch form
 // also took large batches and its p50 at 70% load rose from 170-187 us to
 // 224-242 us.
 constexpr uint64_t kDirectMaxCodewords = uint64_t(1) << 20;
+
+// XCD chunk of the planned-batch launches (consecutive workgroups each XCD
+// takes in turn).  Saturated on the serving trace of the bench, two boxes,
+// two runs each: 16 was 0.007-0.017 of the plain rate above 128 (the chunk
+// tuned for the graph-batched path) on each box, 0.840-0.907 against
+// 0.825-0.891, with 32 and 64 in between and 1 lowest.  Served batches are many small requests at random
+// places on four streams at once, so they keep a chunk of their own.
+constexpr uint32_t kServeXcdChunk = 16;
 
 // Arrivals a trace replay submits between two progress calls.
 constexpr uint32_t kSubmitBurst = 256;
@@ -245,7 +253,7 @@ void fail_batch(hamming_server* s, uint64_t first, uint32_t n, int status)
 int launch(hamming_server* s)
 {
     int schedule = 0, use_graph = 0;
-    uint32_t xcd_chunk = 0, grid_cap = 0;
+    uint32_t xcd_chunk = 0, grid_cap = 0;   // only the schedule applies to served batches
     if (hamming_batch_config_get(&schedule, &xcd_chunk, &grid_cap, &use_graph) != HAMMING_OK) return HAMMING_EDEVICE;
     for (auto& sl : s->slots) {
         if (sl.busy || s->next_admit == s->next_id) continue;
@@ -276,7 +284,7 @@ int launch(hamming_server* s)
         if (n <= hm::kSmallBatchMax && cws <= kDirectMaxCodewords)
             rc = launch_small(s, descs, n, schedule, sl.stream);
         else
-            rc = launch_planned(s, sl, n, schedule, xcd_chunk);
+            rc = launch_planned(s, sl, n, schedule, kServeXcdChunk);
         if (rc == HAMMING_OK && hipEventRecord(sl.done, sl.stream) != hipSuccess) rc = HAMMING_EDEVICE;
         if (rc != HAMMING_OK) {
             (void)hipGetLastError();
