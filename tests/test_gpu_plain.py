@@ -265,6 +265,39 @@ def test_tuner_applies_and_persists_valid_shapes(gpu_device, tmp_path):
         hm.hamming_batch_config_set(*old_batch)
 
 
+def test_tuner_batch_only_keeps_the_loaded_plain_lines(gpu_device, tmp_path):
+    """A run that tunes only the batched decode writes the plain shapes back as
+    the cache it loaded held them, times included (the bench's traffic record
+    is keyed on those lines), and a batch shape the library accepts."""
+    import json
+    import os
+
+    import torch
+
+    shipped = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                           "paper_1412_6862_amd", "tuned_shapes.json")
+    old_plain = {r: hm.hamming_plain_config_get(r) for r in range(3, 8)}
+    old_batch = hm.hamming_batch_config_get()
+    old_chunk = hm.hamming_batch_chunk_get()
+    path = str(tmp_path / "batch_only.json")
+    try:
+        hm.hamming_tune_load(shipped)
+        hm.hamming_tune(path, 2)
+        torch.cuda.synchronize()
+        want = [ln for ln in open(shipped).read().splitlines() if ln.startswith(('{"device"', '{"plain"'))]
+        got = open(path).read().splitlines()
+        assert [ln for ln in got if ln.startswith(('{"device"', '{"plain"'))] == want
+        batch = [json.loads(ln) for ln in got if ln.startswith('{"batch"')]
+        assert len(batch) == 1 and batch[0]["batch"] in (0, 1, 2, 3) and batch[0]["ms"] > 0
+        assert batch[0]["xcd_chunk"] in (1, 8, 16, 32, 64, 128)
+        assert hm.hamming_batch_config_get()[:2] == (batch[0]["batch"], batch[0]["xcd_chunk"])
+    finally:
+        for r in range(3, 8):
+            hm.hamming_plain_config_set(r, *old_plain[r])
+        hm.hamming_batch_config_set(*old_batch)
+        hm.hamming_batch_chunk_set(old_chunk)
+
+
 @pytest.mark.parametrize("r", [4, 6])
 def test_plain_parity_2p28_sampled(gpu_device, r):
     """The largest packet of the size sweep, 2^28 codewords, generated and
