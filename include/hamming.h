@@ -551,10 +551,11 @@ uint64_t hamming_server_now_ns(void);
  * outlive the server.  The server allocates per-slot streams, descriptor
  * arrays, pinned staging and workspaces; hamming_server_destroy frees them.
  * Before returning it runs an empty kernel of the batched decode's code
- * object and waits for it, so that loading that object (once per process) is
- * not charged to the first batch.  Returns HAMMING_OK, HAMMING_EINVAL (bad
- * config, NULL pointer), HAMMING_EALIGN, HAMMING_ENOMEM or HAMMING_EDEVICE
- * (the start-up launch failed).
+ * object and one plan-sized copy on each slot's stream, and waits for them,
+ * so that those one-time costs (loading the code object, a stream's first
+ * copy) are not charged to the first batches.  Returns HAMMING_OK,
+ * HAMMING_EINVAL (bad config, NULL pointer), HAMMING_EALIGN, HAMMING_ENOMEM
+ * or HAMMING_EDEVICE (a start-up launch or copy failed).
  */
 int hamming_server_create(const hamming_server_config *config, const uint64_t *cw_pool,
                           uint64_t cw_pool_words, void *output_pool, uint64_t output_pool_bytes,
